@@ -1,0 +1,387 @@
+"""Pins of the oracle against what the paper and mathematics fix, independent of
+the oracle's own code: published Philox answers, brute-force enumeration of the
+L = 2 lattice, closed forms (E_Delta marginal, beta = 0 density of states,
+Ising limit, T -> 0 crossing at Delta_0 = 3), exact detailed balance, and exact
+canonical expectation values for the reweighting.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import l2_exact
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def test_philox_known_answers():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(t, 16) for t in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        assert oracle.philox4x32_10(r[0:4], r[4:6]) == r[6:10]
+
+
+def test_initial_spins_uniform_ternary():
+    L, n = 8, 16
+    job = oracle.OracleJob(L, 2.0, n, seed=123)
+    vals, counts = np.unique(job.spins, return_counts=True)
+    assert list(vals) == [-1, 0, 1]
+    frac = counts / job.spins.size
+    assert np.all(np.abs(frac - 1 / 3) < 0.02)
+    # different walkers and seeds give different lattices
+    assert not np.array_equal(job.spins[0], job.spins[1])
+    other = oracle.OracleJob(L, 2.0, 1, seed=124)
+    assert not np.array_equal(job.spins[0], other.spins[0])
+
+
+# --------------------------------------------------------------------------
+# Lattice, colouring, energies (Eq. (1))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 7, 9])
+def test_colour_major_order_is_proper(L):
+    V = L ** 3
+    order = oracle.order(L)
+    assert sorted(order.tolist()) == list(range(V))
+    C = oracle.num_colours(L)
+    assert C == (2 if L % 2 == 0 else 3)
+    # recover colour classes as maximal runs and check no two neighbours share one
+    pos = np.empty(V, dtype=np.int64)
+    pos[order] = np.arange(V)
+
+    def nbrs(i):
+        x, y, z = i % L, (i // L) % L, i // (L * L)
+        for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            yield ((x + dx) % L) + L * (((y + dy) % L) + L * ((z + dz) % L))
+
+    # class of a site = its colour under the documented colouring
+    def colour(i):
+        x, y, z = i % L, (i // L) % L, i // (L * L)
+        if L % 2 == 0:
+            return (x + y + z) % 2
+        f = lambda t: 2 if t == L - 1 else t % 2
+        return (f(x) + f(y) + f(z)) % 3
+
+    cols = [colour(int(i)) for i in order]
+    assert cols == sorted(cols)  # colour-major
+    for i in range(V):
+        for j in nbrs(i):
+            assert colour(i) != colour(j)
+    # within a class, ascending site index (z, then y, then x)
+    for c in range(C):
+        sites = [int(i) for i in order if colour(int(i)) == c]
+        assert sites == sorted(sites)
+
+
+def test_l2_energies_match_enumeration_and_closed_forms():
+    ej = np.array([oracle.energies(2, s)[0] for s in l2_exact.STATES])
+    ed = np.array([oracle.energies(2, s)[1] for s in l2_exact.STATES])
+    m = np.array([oracle.energies(2, s)[2] for s in l2_exact.STATES])
+    assert np.array_equal(ej, l2_exact.EJ)
+    assert np.array_equal(ed, l2_exact.ED)
+    assert np.array_equal(m, l2_exact.M)
+    assert ej.min() == -24 and ej.max() == 24
+    # E_Delta marginal: C(8, E) 2^E
+    counts = np.bincount(ed, minlength=9)
+    assert counts.tolist() == [math.comb(8, E) * 2 ** E for E in range(9)]
+
+
+@pytest.mark.parametrize("L", [3, 4, 5, 6])
+def test_energies_closed_forms(L):
+    V = L ** 3
+    ones = np.ones(V, dtype=np.int8)
+    assert oracle.energies(L, ones) == (-3 * V, V, V)
+    assert oracle.energies(L, -ones) == (-3 * V, V, -V)
+    assert oracle.energies(L, 0 * ones) == (0, 0, 0)
+    if L % 2 == 0:
+        x, y, z = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+        idx = (x + L * (y + L * z)).ravel()
+        stag = np.empty(V, dtype=np.int8)
+        stag[idx] = np.where(((x + y + z) % 2).ravel() == 0, 1, -1)
+        assert oracle.energies(L, stag) == (3 * V, V, 0)
+    # one flipped spin in the ferromagnet costs 2 * 6 bonds
+    s = ones.copy()
+    s[0] = -1
+    assert oracle.energies(L, s)[0] == -3 * V + 12
+
+
+# --------------------------------------------------------------------------
+# Acceptance: exact detailed balance of the single-site kernel on L = 2
+# --------------------------------------------------------------------------
+def _acceptance(u_accept, dEJ, d, E, tabs):
+    """Exact fraction of u31 in [0, 2^31) accepted (the rule is monotone in u31)."""
+    Bp, Rp, Rm = tabs
+    lo, hi = 0, 1 << 31  # count = first u that is rejected
+    if u_accept(hi - 1, dEJ, d, E, Bp, Rp, Rm):
+        return 1.0
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if u_accept(mid, dEJ, d, E, Bp, Rp, Rm):
+            lo = mid + 1
+        else:
+            hi = mid
+    return lo / float(1 << 31)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.11])
+def test_detailed_balance_l2(beta):
+    rng = np.random.default_rng(7)
+    lnW = rng.normal(0.0, 1.5, size=9)
+    tabs = oracle.tables(8, beta, lnW)
+    states, ej, ed = l2_exact.STATES, l2_exact.EJ, l2_exact.ED
+    index = {tuple(s): k for k, s in enumerate(states.tolist())}
+    for _ in range(300):
+        a = int(rng.integers(len(states)))
+        i = int(rng.integers(8))
+        sa = states[a].tolist()
+        new = [v for v in (-1, 0, 1) if v != sa[i]][int(rng.integers(2))]
+        sb = list(sa)
+        sb[i] = new
+        b = index[tuple(sb)]
+        dEJ = int(ej[b] - ej[a])
+        d = int(ed[b] - ed[a])
+        A_ab = _acceptance(oracle.accept, dEJ, d, int(ed[a]), tabs)
+        A_ba = _acceptance(oracle.accept, -dEJ, -d, int(ed[b]), tabs)
+        r = math.exp(-beta * dEJ + lnW[ed[b]] - lnW[ed[a]])  # pi(b) / pi(a)
+        tol = 2.0 ** -31 + 1e-12
+        assert abs(A_ab - min(1.0, r)) <= tol
+        assert abs(A_ba - min(1.0, 1.0 / r)) <= tol
+
+
+# --------------------------------------------------------------------------
+# The full colour-major sweep samples exp(-beta E_J) W(E_Delta)
+# --------------------------------------------------------------------------
+def test_sweep_stationary_distribution_l2():
+    beta = 0.5
+    rng = np.random.default_rng(11)
+    lnW = rng.normal(0.0, 1.0, size=9)
+    job = oracle.OracleJob(2, 1.0 / beta, 16, seed=5, lnW=lnW)
+    job.sweep(200, record=False)  # equilibrate
+    job.sweep(20000, record=True)
+    s = job.bin_sums()
+    H = np.array(s["H"], dtype=float)
+    p_hat = H / H.sum()
+    a = -beta * l2_exact.EJ + lnW[l2_exact.ED]
+    w = np.exp(a - a.max())
+    p = np.array([w[l2_exact.ED == E].sum() for E in range(9)]) / w.sum()
+    assert np.all(np.abs(p_hat - p) < 0.004 + 0.05 * p)
+    # conditional mean of E_J in each E_Delta bin
+    for E in range(9):
+        sel = l2_exact.ED == E
+        exact = (w[sel] * l2_exact.EJ[sel]).sum() / w[sel].sum()
+        if H[E] > 2000:
+            assert abs(s["SJ"][E] / H[E] - exact) < 0.25
+
+
+def test_flat_histogram_at_exact_weights_l2():
+    beta = 0.7
+    lnW = -l2_exact.ln_g_beta(beta)
+    job = oracle.OracleJob(2, 1.0 / beta, 16, seed=9, lnW=lnW)
+    job.sweep(200)
+    job.take_hist()
+    job.sweep(20000)
+    h = job.take_hist()
+    frac = h / h.sum()
+    assert np.all(np.abs(frac - 1.0 / 9) < 0.01)
+
+
+@pytest.mark.parametrize("L", [3, 5])
+def test_flat_histogram_beta0_closed_form(L):
+    """At beta = 0 the E_Delta density of states is C(V,E) 2^E for any L, so
+    lnW = -ln g gives a flat E_Delta histogram (odd L: 3-colour order)."""
+    V = L ** 3
+    lnW = np.array([-(math.lgamma(V + 1) - math.lgamma(E + 1) - math.lgamma(V - E + 1) + E * math.log(2))
+                    for E in range(V + 1)])
+    job = oracle.OracleJob(L, float("inf"), 16, seed=3, lnW=lnW)
+    job.sweep(200)
+    job.take_hist()
+    job.sweep(8000 if L == 3 else 16000)
+    h = job.take_hist()
+    frac = h / h.sum()
+    assert np.all(np.abs(frac - 1.0 / (V + 1)) < 0.25 / (V + 1))
+
+
+@pytest.mark.parametrize("L,T", [(3, 2.0), (4, 1.0), (5, 1.4182), (6, 0.9)])
+def test_tracked_energies_equal_recomputation(L, T):
+    rng = np.random.default_rng(L)
+    V = L ** 3
+    lnW = np.cumsum(rng.normal(0.0, 0.3, size=V + 1))
+    job = oracle.OracleJob(L, T, 6, seed=17, lnW=lnW)
+    job.sweep(50, record=True)
+    for w in range(job.n_walkers):
+        assert tuple(job.state[w, :3]) == oracle.energies(L, job.spins[w])
+        assert job.state[w, 3] == 50
+    assert job.hist.sum() == 6 * 50
+    assert job.acc[0].sum() == 6 * 50
+
+
+def test_thread_split_is_invisible():
+    a = oracle.OracleJob(4, 2.0, 7, seed=1, n_threads=1)
+    b = oracle.OracleJob(4, 2.0, 7, seed=1, n_threads=3)
+    a.sweep(30, record=True)
+    b.sweep(30, record=True)
+    assert np.array_equal(a.spins, b.spins) and np.array_equal(a.state, b.state)
+    assert np.array_equal(a.hist, b.hist) and np.array_equal(a.acc, b.acc)
+    assert np.array_equal(a.sm4_lo, b.sm4_lo) and np.array_equal(a.sm4_hi, b.sm4_hi)
+
+
+# --------------------------------------------------------------------------
+# Weight recursion and flatness
+# --------------------------------------------------------------------------
+def test_recursion_converges_to_beta0_density_of_states():
+    L, V = 3, 27
+    job = oracle.OracleJob(L, float("inf"), 16, seed=21)
+    flat = 0.0
+    for it in range(30):
+        job.sweep(3000)
+        flat = job.update_weights(job.take_hist())
+    assert flat > 0.5
+    exact = np.array([-math.log(2.0 * (V - E + 1) / E) for E in range(1, V + 1)])
+    diffs = np.diff(job.lnW)
+    assert np.all(np.abs(diffs - exact) < 0.3), np.max(np.abs(diffs - exact))
+
+
+def test_recursion_converges_to_exact_weights_l2():
+    beta = 0.5
+    job = oracle.OracleJob(2, 1.0 / beta, 16, seed=4)
+    for it in range(25):
+        job.sweep(4000)
+        job.update_weights(job.take_hist())
+    target = -l2_exact.ln_g_beta(beta)
+    assert np.all(np.abs(np.diff(job.lnW) - np.diff(target)) < 0.15)
+
+
+def test_flatness_special_cases():
+    job = oracle.OracleJob(2, 1.0, 1, seed=0)
+    lnW = job.lnW.copy()
+    assert job.update_weights(np.full(9, 7, dtype=np.int64)) == 1.0
+    # a flat histogram shifts every log-weight by the same amount
+    assert np.allclose(job.lnW - lnW, -math.log(7.0), atol=0, rtol=0)
+    h = np.full(9, 10, dtype=np.int64)
+    h[3] = 0
+    before = job.lnW.copy()
+    assert job.update_weights(h) == 0.0
+    assert job.lnW[3] == before[3]
+    h = np.array([1, 2, 3, 4, 5, 6, 7, 8, 9], dtype=np.int64)
+    assert abs(job.update_weights(h) - 1.0 / 5.0) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Reweighting against exact canonical values (Sec. II; Eqs. (FieldDerivative), (sph))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("T", [0.8, 2.0])
+def test_reweight_exact_l2(T):
+    beta = 1.0 / T
+    rng = np.random.default_rng(3)
+    lnW = rng.normal(0.0, 2.0, size=9)
+    sums = l2_exact.muca_bin_sums(beta, lnW, n=1e6)
+    deltas = np.linspace(-1.0, 4.5, 23)
+    out = oracle.reweight(8, beta, lnW, sums, deltas)
+    col = {k: i for i, k in enumerate(oracle.OBS_FIELDS)}
+    for r, delta in zip(out, deltas):
+        exact = l2_exact.canonical(beta, delta)
+        assert r[col["delta"]] == delta
+        for k, v in exact.items():
+            assert abs(r[col[k]] - v) <= 1e-9 * max(1.0, abs(v)), (k, delta, r[col[k]], v)
+
+
+def test_field_derivatives_by_finite_differences():
+    beta = 1.0 / 1.3
+    lnW = np.zeros(9)
+    sums = l2_exact.muca_bin_sums(beta, lnW)
+    col = {k: i for i, k in enumerate(oracle.OBS_FIELDS)}
+    h = 1e-4
+    for delta in (1.5, 2.7, 3.3):
+        o = oracle.reweight(8, beta, lnW, sums, [delta - h, delta, delta + h])
+        dEJ = (o[2, col["mean_EJ"]] - o[0, col["mean_EJ"]]) / (2 * h)
+        dC = (o[2, col["C_field"]] - o[0, col["C_field"]]) / (2 * h)
+        assert abs(dEJ - o[1, col["C_field"]]) < 1e-6 * max(1, abs(dEJ))
+        assert abs(dC - o[1, col["dC_dDelta"]]) < 1e-5 * max(1, abs(dC))
+
+
+def test_reweight_ising_limit():
+    """Delta -> -infinity suppresses vacancies: everything comes from bin E = V."""
+    rng = np.random.default_rng(5)
+    V = 27
+    sums = {"H": [int(v) for v in rng.integers(1, 50, size=V + 1)], "V": V}
+    for k in ("SJ", "SJJ", "SA", "SM2", "SM4"):
+        sums[k] = [int(v) for v in rng.integers(-100 if k == "SJ" else 0, 1000, size=V + 1)]
+    lnW = rng.normal(0.0, 3.0, size=V + 1)
+    o = oracle.reweight(V, 0.5, lnW, sums, [-1000.0])[0]
+    col = {k: i for i, k in enumerate(oracle.OBS_FIELDS)}
+    H = sums["H"][V]
+    assert o[col["mean_ED"]] == V
+    assert abs(o[col["mean_EJ"]] - sums["SJ"][V] / H) < 1e-12 * abs(sums["SJ"][V] / H)
+    assert abs(o[col["mean_M2"]] - sums["SM2"][V] / H) < 1e-12 * abs(sums["SM2"][V] / H)
+    assert abs(o[col["C_field"]]) < 1e-150 and abs(o[col["var_ED"]]) < 1e-150
+    assert abs(o[col["edge_weight"]] - 1.0) < 1e-12
+
+
+def test_reweight_canonical_identity():
+    """Weights lnW = -beta Delta0 E make the chain canonical at Delta0, so
+    reweighting to Delta0 gives plain sample means."""
+    L, T, D0 = 3, 1.5, 2.2
+    beta = 1.0 / T
+    V = L ** 3
+    lnW = np.array([-(beta * D0) * E for E in range(V + 1)])
+    job = oracle.OracleJob(L, T, 8, seed=31, lnW=lnW)
+    job.sweep(50)
+    job.sweep(400, record=True)
+    s = job.bin_sums()
+    o = oracle.reweight(V, beta, lnW, s, [D0])[0]
+    col = {k: i for i, k in enumerate(oracle.OBS_FIELDS)}
+    n = sum(s["H"])
+    assert abs(o[col["mean_EJ"]] - sum(s["SJ"]) / n) < 1e-12 * abs(sum(s["SJ"]) / n)
+    assert abs(o[col["mean_ED"]] - sum(E * h for E, h in enumerate(s["H"])) / n) < 1e-12 * V
+    assert abs(o[col["mean_M4"]] - sum(s["SM4"]) / n) < 1e-12 * abs(sum(s["SM4"]) / n)
+
+
+@pytest.mark.parametrize("T", [0.2, 0.25, 0.3])
+def test_zero_temperature_crossing_delta0_eq_3(T):
+    """At low T the ground state switches from all +-1 (degeneracy 2) to all 0
+    at Delta_0 = zJ/2 = 3 (Sec. I); on L = 2 the equal-weight point sits at
+    3 + T ln 2 / V up to corrections of order exp(-3 beta)."""
+    beta = 1.0 / T
+    lnW = -l2_exact.ln_g_beta(beta)  # flat-histogram weights
+    sums = l2_exact.muca_bin_sums(beta, lnW)
+    col = {k: i for i, k in enumerate(oracle.OBS_FIELDS)}
+    lo, hi = 2.5, 3.5
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        eD = oracle.reweight(8, beta, lnW, sums, [mid])[0][col["mean_ED"]]
+        if eD > 4.0:
+            lo = mid
+        else:
+            hi = mid
+    assert abs(0.5 * (lo + hi) - (3.0 + T * math.log(2.0) / 8)) < T * math.exp(-3.0 * beta)
+
+
+# --------------------------------------------------------------------------
+# Whole pipeline on L = 2: iterate weights, record, reweight vs enumeration
+# --------------------------------------------------------------------------
+def test_muca_pipeline_l2_matches_enumeration():
+    T = 1.0
+    beta = 1.0 / T
+    job = oracle.OracleJob(2, T, 16, seed=2)
+    for it in range(12):
+        job.sweep(3000)
+        job.update_weights(job.take_hist())
+    job.take_hist()
+    job.sweep(20000, record=True)
+    deltas = [1.0, 2.0, 2.8, 3.0, 3.2, 4.0]
+    out = job.reweight(deltas)
+    col = {k: i for i, k in enumerate(oracle.OBS_FIELDS)}
+    for r, d in zip(out, deltas):
+        ex = l2_exact.canonical(beta, d)
+        assert abs(r[col["mean_EJ"]] - ex["mean_EJ"]) < 0.2
+        assert abs(r[col["mean_ED"]] - ex["mean_ED"]) < 0.1
+        assert abs(r[col["C_field"]] - ex["C_field"]) < 0.08 * max(1.0, abs(ex["C_field"]))
+        assert abs(r[col["mean_M2"]] - ex["mean_M2"]) < 0.05 * max(1.0, ex["mean_M2"])
