@@ -1,0 +1,208 @@
+/*
+ * muca.h -- C ABI of libmuca: parallel multicanonical (MUCA) sampling of the
+ * three-dimensional Blume-Capel model on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: J. Zierenberg, N. G. Fytas, W. Janke, "Parallel multicanonical study
+ * of the three-dimensional Blume-Capel model".
+ *   Sec. I, Eq. (1)  model H = -J sum_<ij> s_i s_j + Delta sum_i s_i^2 = E_J + Delta E_Delta,
+ *                    s_i in {-1, 0, +1}, L^3 simple cubic lattice, periodic, J = k_B = 1.
+ *   Sec. II          multicanonical weights W(E_Delta) at fixed beta replace
+ *                    exp(-beta Delta E_Delta); W is adapted iteratively to a flat
+ *                    E_Delta histogram (E_Delta is an integer in [0, V]); many
+ *                    independent walkers share W and merge their histograms
+ *                    (parallel MUCA); time-series reweighting gives canonical
+ *                    expectation values at any Delta.
+ *   Eq. (FieldDerivative), Eq. (sph)  field derivatives, C(Delta) = d<E_J>/dDelta.
+ *
+ * Conventions fixed where the paper is silent (identical in the test oracle):
+ *   site i = x + L(y + Lz); colour-major visiting order (even L: colour (x+y+z) mod 2;
+ *   odd L: f(t) = t mod 2 for t <= L-2, f(L-1) = 2, colour (f(x)+f(y)+f(z)) mod 3;
+ *   colours ascending, then z, y, x ascending); proposal = the b-th (ascending) of the
+ *   two other spin values; Philox4x32-10 with key (seed lo32, seed hi32): the attempt
+ *   at position p of sweep s of walker w uses word p&3 of block (p>>2, w, s, 0),
+ *   b = bit 0, u31 = bits 1..31; initial spin of site i: word i&3 of block
+ *   (i>>2, w, 0, 1), s_i = floor(3x / 2^32) - 1; accept iff
+ *   (double)u31 < B'[dE_J + 12] * R_d[E_Delta] with B'[k] = 2^31 exp(-beta k),
+ *   R_+[E] = exp(lnW[E+1] - lnW[E]), R_-[E] = exp(lnW[E-1] - lnW[E]), R_0 = 1.
+ *
+ * General rules:
+ *   - Every call returns int: MUCA_OK (0) or a negative MUCA_E_* code.  No
+ *     exception or abort crosses the ABI.  muca_strerror() describes a code; after
+ *     MUCA_E_DEVICE it also carries the HIP error of the failing call.
+ *   - Device memory is allocated by the caller (e.g. PyTorch) and borrowed: sizes
+ *     come from muca_query_sizes, the pointers must stay valid until muca_free and
+ *     are never freed by the library.  Device buffers need 256-byte alignment.
+ *   - Host arrays belong to the caller; the library copies from or into them during
+ *     the call and keeps no reference.
+ *   - All device work of a job is ordered on the caller's HIP stream given to
+ *     muca_init.  Calls return after enqueueing, except those marked "synchronises".
+ *   - A job must not be used from two threads at once; distinct jobs are independent.
+ */
+#ifndef MUCA_H
+#define MUCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MUCA_OK 0
+#define MUCA_E_INVAL (-1)       /* bad argument: L, T, n_walkers, null pointer, range */
+#define MUCA_E_UNSUPPORTED (-2) /* valid request this build does not implement */
+#define MUCA_E_SIZE (-3)        /* buffer too small / too large for a fixed limit */
+#define MUCA_E_STATE (-4)       /* call out of order (e.g. reweight with no recorded data) */
+#define MUCA_E_OVERFLOW (-5)    /* a counter would overflow (n_sweeps per call) */
+#define MUCA_E_DEVICE (-6)      /* a HIP call failed or a kernel reported an error */
+
+#define MUCA_L_MIN 2
+#define MUCA_L_MAX 32
+#define MUCA_MAX_SWEEPS_PER_CALL ((int64_t)1 << 40)
+
+/* muca_sweep flags */
+#define MUCA_RECORD 1u /* also accumulate the per-bin production sums used by muca_reweight */
+
+typedef struct muca_job muca_job;
+
+typedef struct {
+    int32_t L;         /* MUCA_L_MIN..MUCA_L_MAX; V = L^3 */
+    double T;          /* temperature > 0, or +INFINITY for beta = 0; beta = 1.0 / T in FP64 */
+    int32_t n_walkers; /* >= 1 independent walkers sharing one weight function */
+    uint64_t seed;     /* Philox key: k0 = low 32 bits, k1 = high 32 bits */
+    int32_t max_delta; /* largest n_delta a muca_reweight call may ask for, 0..65536 */
+} muca_params;
+
+/* Caller-owned device buffers, sized by muca_query_sizes (bytes, 256-aligned). */
+typedef struct {
+    void *lattice;      /* spins, n_walkers x Vp int8 (Vp = V rounded up to 16), colour-major order */
+    void *walker_state; /* n_walkers x 4 int32: E_J, E_Delta, M, sweeps done (uint32) */
+    void *hist;         /* V+1 uint64: E_Delta histogram of the current iteration */
+    void *tables;       /* thresholds B'[25], R_-/R_+[V+1], lnW[V+1], neighbour and site tables */
+    void *accum;        /* 7 x (V+1) uint64 per-bin production sums: H, SJ, SJJ, S|M|, SM2, SM4 lo, SM4 hi */
+    void *obs;          /* reweighting scratch: max_delta x (1 + MUCA_N_OBS) doubles */
+} muca_dev_buffers;
+
+/* Observables of one reweighting point (Sec. II; Eqs. (FieldDerivative), (sph)). */
+#define MUCA_N_OBS 15
+typedef struct {
+    double delta;     /* the crystal field Delta */
+    double mean_EJ;   /* <E_J> */
+    double mean_ED;   /* <E_Delta> */
+    double mean_E;    /* <E_J + Delta E_Delta> */
+    double mean_EJ2;  /* <E_J^2> */
+    double var_EJ;    /* <E_J^2> - <E_J>^2 */
+    double var_ED;    /* <E_Delta^2> - <E_Delta>^2 */
+    double C_field;   /* C(Delta) = d<E_J>/dDelta = -beta (<E_J E_Delta> - <E_J><E_Delta>), Eq. (sph) */
+    double dC_dDelta; /* dC/dDelta = beta^2 <(E_J - <E_J>)(E_Delta - <E_Delta>)^2> */
+    double cV;        /* beta^2 Var(E) / V, E = E_J + Delta E_Delta */
+    double mean_absM; /* <|M|> */
+    double mean_M2;   /* <M^2> */
+    double mean_M4;   /* <M^4> */
+    double binder_U4; /* 1 - <M^4> / (3 <M^2>^2); NaN when <M^2> = 0 */
+    double edge_weight; /* reweighted probability of the first + last visited E_Delta bin */
+} muca_obs;
+
+/* Byte sizes of the six device buffers for params.  Returns MUCA_E_INVAL on bad
+ * params.  Any size pointer may be NULL. */
+int muca_query_sizes(const muca_params *params, size_t *lattice_bytes, size_t *state_bytes,
+                     size_t *hist_bytes, size_t *tables_bytes, size_t *accum_bytes,
+                     size_t *obs_bytes);
+
+/* Create a job (steps "init" and "tables", Sec. I-II).  Draws the initial
+ * lattices on the device (Philox, counter tag 1), computes E_J, E_Delta, M by
+ * full recomputation, zeroes hist and accum, and uploads the threshold tables
+ * for lnW_host (V+1 doubles, copied; NULL = flat, lnW = 0).  stream is a
+ * hipStream_t (NULL = default stream).  On success *out owns host resources
+ * released by muca_free.  Synchronises. */
+int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const double *lnW_host,
+              void *stream, muca_job **out);
+
+/* Step "sweep" + "measure" (Sec. II): n_sweeps (0..MUCA_MAX_SWEEPS_PER_CALL)
+ * sweeps of every walker, V single-spin-flip Metropolis attempts each under
+ * exp(-beta E_J) W(E_Delta); after each sweep every walker adds one entry at its
+ * E_Delta to hist.  With MUCA_RECORD, the per-bin production sums are added to as
+ * well.  Asynchronous on the job's stream. */
+int muca_sweep(muca_job *job, int64_t n_sweeps, uint32_t flags);
+
+/* Step "reduce" (Sec. II, parallel MUCA merge): copy the walker-summed histogram
+ * (V+1 int64) to hist_host; if reset != 0 zero it on the device afterwards.
+ * Synchronises; reports MUCA_E_DEVICE if a kernel flagged an internal error. */
+int muca_reduce_hist(muca_job *job, int64_t *hist_host, int32_t reset);
+
+/* Step "update" (Sec. II, iterative weights): lnW[E] -= log(H[E]) where H[E] > 0
+ * (plain recursion W <- W / H) on the job's weights, then re-upload the
+ * threshold tables.  hist (V+1, non-negative) is the merged histogram of the
+ * iteration; lnW_out (V+1, may be NULL) receives the new weights; flatness_out
+ * (may be NULL) receives min_E H[E] / mean_E H[E] over [0, V] of hist.  The
+ * production sums are cleared (they belong to the weights they were sampled
+ * under).  Host FP64; the upload is asynchronous. */
+int muca_update_weights(muca_job *job, const int64_t *hist, double *lnW_out, double *flatness_out);
+
+/* Replace the job's weights by lnW (V+1 finite doubles) and re-upload the
+ * thresholds; clears the production sums.  For weights carried over from an
+ * earlier run, a checkpoint, or a start tilted towards some Delta. */
+int muca_set_weights(muca_job *job, const double *lnW);
+
+/* Copy the job's current weights (V+1 doubles) to lnW_out. */
+int muca_get_weights(const muca_job *job, double *lnW_out);
+
+/* Step "reweight" (Sec. II time-series reweighting; Eqs. (FieldDerivative),
+ * (sph)): canonical expectation values at (beta, delta[k]) for k < n_delta from
+ * the production sums and the weights they were recorded under.  Runs one
+ * device block per Delta.  n_delta in 1..max_delta.  MUCA_E_STATE when nothing
+ * has been recorded.  Synchronises. */
+int muca_reweight(muca_job *job, const double *delta, int32_t n_delta, muca_obs *out);
+
+/* Copy walker state to the host: spins (n_walkers x V int8, site-indexed
+ * i = x + L(y + Lz), may be NULL) and state (n_walkers x 4 int64: E_J, E_Delta,
+ * M, sweeps done; may be NULL).  Synchronises. */
+int muca_read_state(muca_job *job, int8_t *spins, int64_t *state);
+
+/* Overwrite walker state from the host (checkpoint resume).  spins as in
+ * muca_read_state with values in {-1,0,1}; state's E_J, E_Delta, M must equal
+ * the energies of the spins (not checked on the device) and sweeps done < 2^32.
+ * Synchronises. */
+int muca_write_state(muca_job *job, const int8_t *spins, const int64_t *state);
+
+/* Copy the production sums to the host: sums (5 x (V+1) int64: H, SJ, SJJ, S|M|,
+ * SM2) and sm4 (2 x (V+1) uint64: low words, then high words of the 128-bit
+ * sums of M^4); either may be NULL.  Synchronises. */
+int muca_read_accum(muca_job *job, int64_t *sums, uint64_t *sm4);
+
+/* Zero the production sums.  Asynchronous. */
+int muca_reset_accum(muca_job *job);
+
+/* Launch shape of the sweep kernel (results do not depend on it):
+ * waves_per_walker in {1, 2, 4} (64, 128 or 256 lanes cooperate on one walker),
+ * blocks_per_lane in {1, 2} (4 or 8 consecutive sites per lane per pass),
+ * lds_tables: 1 = thresholds and neighbour table in LDS, 0 = read through the
+ * caches, -1 = automatic.  MUCA_E_SIZE if the shape needs more LDS than a CU has. */
+int muca_set_launch(muca_job *job, int32_t waves_per_walker, int32_t blocks_per_lane,
+                    int32_t lds_tables);
+
+/* Current launch shape and its LDS bytes per block. */
+int muca_get_launch(const muca_job *job, int32_t *waves_per_walker, int32_t *blocks_per_lane,
+                    int32_t *lds_tables, int32_t *lds_bytes);
+
+/* Host-only: the threshold tables of the acceptance rule for (L, T, lnW):
+ * Bp (25), Rp (V+1) and Rm (V+1) doubles.  Used to check that the tables are
+ * bitwise identical to an independent implementation on the same host. */
+int muca_host_tables(int32_t L, double T, const double *lnW, double *Bp, double *Rp, double *Rm);
+
+/* Host-only: the colour-major visiting order, order[p] = site index (V int32). */
+int muca_host_order(int32_t L, int32_t *order);
+
+/* Human-readable description of an error code (static storage; thread-local
+ * detail for MUCA_E_DEVICE). */
+const char *muca_strerror(int code);
+
+/* Release the job's host resources.  Waits for the job's queued work first.
+ * NULL is ignored.  The caller's device buffers are not touched. */
+void muca_free(muca_job *job);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MUCA_H */

@@ -69,13 +69,13 @@ def lib():
         L.orc_energies.restype = None
         L.orc_init_walker.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, i8p]
         L.orc_init_walker.restype = None
-        L.orc_init.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, i8p, i64p]
+        L.orc_init.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, i8p, i64p]
         L.orc_init.restype = None
         L.orc_tables.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp]
         L.orc_tables.restype = None
         L.orc_accept.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_accept.restype = ctypes.c_int
-        L.orc_run.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_int, i8p, i64p,
+        L.orc_run.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, i8p, i64p,
                               dp, ctypes.c_int64, ctypes.c_int, i64p, i64p, u64p, u64p, ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
         L.orc_update_weights.argtypes = [ctypes.c_int, i64p, dp]
@@ -145,16 +145,19 @@ def beta_of(T: float) -> float:
 # A multicanonical job: walkers, histograms, weights
 # --------------------------------------------------------------------------
 class OracleJob:
-    """All walkers of one (L, T) multicanonical job, held on the host."""
+    """Walkers [first_walker, first_walker + n_walkers) of one (L, T)
+    multicanonical job, held on the host."""
 
-    def __init__(self, L: int, T: float, n_walkers: int, seed: int, lnW=None, n_threads: int = 0):
+    def __init__(self, L: int, T: float, n_walkers: int, seed: int, lnW=None, n_threads: int = 0,
+                 first_walker: int = 0):
         self.L, self.V = L, L ** 3
         self.T, self.beta = T, beta_of(T)
         self.n_walkers, self.seed = n_walkers, seed
         self.n_threads = n_threads
+        self.first_walker = first_walker
         self.spins = np.zeros((n_walkers, self.V), dtype=np.int8)
         self.state = np.zeros((n_walkers, 4), dtype=np.int64)
-        lib().orc_init(L, seed, n_walkers, _ptr(self.spins, ctypes.c_int8), _ptr(self.state, ctypes.c_int64))
+        lib().orc_init(L, seed, first_walker, n_walkers, _ptr(self.spins, ctypes.c_int8), _ptr(self.state, ctypes.c_int64))
         self.lnW = np.zeros(self.V + 1) if lnW is None else np.array(lnW, dtype=np.float64)
         self.hist = np.zeros(self.V + 1, dtype=np.int64)
         self.reset_accum()
@@ -168,7 +171,7 @@ class OracleJob:
     def sweep(self, n_sweeps: int, record: bool = False):
         """n_sweeps sweeps of every walker; histogram entries are added to self.hist."""
         self.threads_used = lib().orc_run(
-            self.L, self.beta, self.seed, self.n_walkers, _ptr(self.spins, ctypes.c_int8),
+            self.L, self.beta, self.seed, self.first_walker, self.n_walkers, _ptr(self.spins, ctypes.c_int8),
             _ptr(self.state, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double), int(n_sweeps),
             1 if record else 0, _ptr(self.hist, ctypes.c_int64), _ptr(self.acc, ctypes.c_int64),
             _ptr(self.sm4_lo, ctypes.c_uint64), _ptr(self.sm4_hi, ctypes.c_uint64), self.n_threads)

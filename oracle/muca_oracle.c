@@ -202,7 +202,8 @@ typedef struct {
     int record;
     int8_t *spins;          /* n_walkers x V, site-indexed */
     int64_t *state;         /* n_walkers x 4: E_J, E_Delta, M, sweeps done */
-    int w_begin, w_end;
+    int w_begin, w_end;     /* local walker indices [w_begin, w_end) */
+    int w_first;            /* global index of local walker 0 */
     int64_t *hist;          /* V+1, private to the thread */
     int64_t *acc;           /* 5 x (V+1): H, SJ, SJJ, SA, SM2, private */
     unsigned __int128 *sm4; /* V+1, private */
@@ -246,7 +247,7 @@ static void *orc_worker(void *arg)
         int8_t *s = t->spins + (size_t)w * t->V;
         int64_t *st = t->state + 4 * (size_t)w;
         for (int64_t n = 0; n < t->n_sweeps; n++) {
-            orc_sweep(t, w, s, st);
+            orc_sweep(t, t->w_first + w, s, st);
             int64_t ej = st[0], ed = st[1], m = st[2];
             t->hist[ed] += 1;
             if (t->record) {
@@ -263,14 +264,15 @@ static void *orc_worker(void *arg)
     return NULL;
 }
 
-/* Run n_sweeps sweeps of walkers [0, n_walkers) under the weights lnW at
+/* Run n_sweeps sweeps of walkers [w_first, w_first + n_walkers) (global
+ * walker indices; spins and state hold these walkers in order) under the weights lnW at
  * inverse temperature beta.  hist (V+1) and, when record != 0, acc
  * (5 x (V+1): H, SJ, SJJ, SA, SM2) and sm4_lo/sm4_hi (V+1 each, the low and
  * high 64 bits of the 128-bit sums of M^4) are added to, not cleared.
  * Walkers are independent between weight updates, so they are split over
  * n_threads threads (0: one per online core); integer sums do not depend on
  * the split.  Returns the number of threads used. */
-int orc_run(int L, double beta, uint64_t seed, int n_walkers, int8_t *spins, int64_t *state,
+int orc_run(int L, double beta, uint64_t seed, int w_first, int n_walkers, int8_t *spins, int64_t *state,
             const double *lnW, int64_t n_sweeps, int record, int64_t *hist, int64_t *acc,
             uint64_t *sm4_lo, uint64_t *sm4_hi, int n_threads)
 {
@@ -295,7 +297,7 @@ int orc_run(int L, double beta, uint64_t seed, int n_walkers, int8_t *spins, int
         orc_task *t = &tasks[k];
         t->L = L; t->V = V; t->seed = seed; t->order = order;
         t->Bp = Bp; t->Rp = Rp; t->Rm = Rm;
-        t->n_sweeps = n_sweeps; t->record = record;
+        t->n_sweeps = n_sweeps; t->record = record; t->w_first = w_first;
         t->spins = spins; t->state = state;
         t->w_begin = (int)((int64_t)n_walkers * k / n_threads);
         t->w_end = (int)((int64_t)n_walkers * (k + 1) / n_threads);
@@ -329,14 +331,14 @@ int orc_run(int L, double beta, uint64_t seed, int n_walkers, int8_t *spins, int
     return n_threads;
 }
 
-/* Initialise n_walkers walkers: spins from orc_init_walker, energies by full
- * recomputation, sweep counter 0. */
-void orc_init(int L, uint64_t seed, int n_walkers, int8_t *spins, int64_t *state)
+/* Initialise walkers [w_first, w_first + n_walkers): spins from
+ * orc_init_walker, energies by full recomputation, sweep counter 0. */
+void orc_init(int L, uint64_t seed, int w_first, int n_walkers, int8_t *spins, int64_t *state)
 {
     int V = L * L * L;
     for (int w = 0; w < n_walkers; w++) {
         int8_t *s = spins + (size_t)w * V;
-        orc_init_walker(L, seed, (uint32_t)w, s);
+        orc_init_walker(L, seed, (uint32_t)(w_first + w), s);
         int64_t e[3];
         orc_energies(L, s, e);
         state[4 * (size_t)w + 0] = e[0];

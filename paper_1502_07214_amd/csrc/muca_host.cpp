@@ -1,0 +1,625 @@
+// Host side of libmuca: argument checks, buffer layout, the colour-major order
+// and neighbour tables, the acceptance thresholds and the multicanonical weight
+// recursion (host FP64), and the ordering of device work on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/muca.h"
+#include "muca_internal.h"
+
+using namespace muca;
+
+static_assert(sizeof(muca_obs) == MUCA_N_OBS * sizeof(double), "muca_obs must be 15 packed doubles");
+
+namespace {
+
+thread_local std::string g_detail;
+
+int fail_device(hipError_t e, const char *what)
+{
+    g_detail = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return MUCA_E_DEVICE;
+}
+
+#define HIP_TRY(expr)                                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return fail_device(e_, #expr); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Lattice geometry (Sec. I: L^3 simple cubic, periodic) and visiting order.
+// ---------------------------------------------------------------------------
+int colour_count(int L) { return (L & 1) ? 3 : 2; }
+
+// Proper colouring: even L by parity of x+y+z; odd L by f(t) = t mod 2 for
+// t < L-1 and f(L-1) = 2, colour = (f(x) + f(y) + f(z)) mod 3.
+int colour_of(int L, int x, int y, int z)
+{
+    if (!(L & 1)) return (x + y + z) & 1;
+    auto f = [L](int t) { return t == L - 1 ? 2 : (t & 1); };
+    return (f(x) + f(y) + f(z)) % 3;
+}
+
+// order[p] = site index at position p; cls[c] = first position of colour c.
+void build_order(int L, std::vector<int> &order, int cls[kMaxClasses + 1])
+{
+    const int V = L * L * L, C = colour_count(L);
+    std::vector<int> count(C + 1, 0);
+    std::vector<int> col(V);
+    for (int i = 0; i < V; ++i) {
+        col[i] = colour_of(L, i % L, (i / L) % L, i / (L * L));
+        count[col[i] + 1]++;
+    }
+    for (int c = 0; c < C; ++c) count[c + 1] += count[c];
+    for (int c = 0; c <= kMaxClasses; ++c) cls[c] = c <= C ? count[c] : V;
+    order.assign(V, 0);
+    std::vector<int> fill(count.begin(), count.end() - 1);
+    for (int i = 0; i < V; ++i) order[fill[col[i]]++] = i;  // ascending i inside each colour
+}
+
+bool params_ok(const muca_params *p)
+{
+    if (!p) return false;
+    if (p->L < MUCA_L_MIN || p->L > MUCA_L_MAX) return false;
+    if (!(p->T > 0.0)) return false;  // rejects NaN and T <= 0; +inf allowed
+    if (p->n_walkers < 1) return false;
+    if (p->max_delta < 0 || p->max_delta > 65536) return false;
+    return true;
+}
+
+double beta_of(double T) { return std::isinf(T) ? 0.0 : 1.0 / T; }
+
+Layout make_layout(const muca_params *p)
+{
+    Layout g{};
+    g.L = p->L;
+    g.V = p->L * p->L * p->L;
+    g.Vp = (int)align_up((size_t)g.V, 16);
+    g.C = colour_count(p->L);
+    g.n_walkers = p->n_walkers;
+    g.max_delta = p->max_delta;
+    const size_t V1 = (size_t)g.V + 1;
+    g.lattice_bytes = align_up((size_t)g.n_walkers * g.Vp, 256);
+    g.state_bytes = align_up((size_t)g.n_walkers * 16, 256);
+    g.hist_bytes = align_up(8 * V1, 256) + 256;  // + error word
+    g.off_bp = 0;
+    g.off_r = 256;
+    g.off_lnw = g.off_r + align_up(16 * V1, 256);
+    g.off_nb = g.off_lnw + align_up(8 * V1, 256);
+    g.off_site = g.off_nb + align_up((size_t)12 * g.Vp, 256);
+    g.tables_bytes = g.off_site + align_up((size_t)2 * g.Vp, 256);
+    g.accum_bytes = align_up(7 * 8 * V1, 256);
+    g.obs_bytes = align_up((size_t)g.max_delta * (1 + MUCA_N_OBS) * 8, 256);
+    if (g.obs_bytes == 0) g.obs_bytes = 256;
+    return g;
+}
+
+// Acceptance thresholds (Sec. II): Bp[k+12] = 2^31 exp(-beta k), k = dE_J in
+// [-12, 12]; Rp[E] = exp(lnW[E+1] - lnW[E]) (0 at E = V); Rm[E] =
+// exp(lnW[E-1] - lnW[E]) (0 at E = 0).
+void compute_tables(int V, double beta, const double *lnW, double *Bp, double *Rp, double *Rm)
+{
+    for (int k = 0; k < 25; ++k) {
+        const double dE = (double)(k - 12);
+        Bp[k] = std::ldexp(std::exp(-(beta * dE)), 31);
+    }
+    for (int E = 0; E <= V; ++E) {
+        Rp[E] = E < V ? std::exp(lnW[E + 1] - lnW[E]) : 0.0;
+        Rm[E] = E > 0 ? std::exp(lnW[E - 1] - lnW[E]) : 0.0;
+    }
+}
+
+int query_max_lds(int device)
+{
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
+        v = 65536;
+    return v;
+}
+
+}  // namespace
+
+struct muca_job {
+    muca_params p;
+    Layout g;
+    double beta;
+    uint32_t k0, k1;
+    int device;
+    int max_lds;
+    int n_cu;
+    hipStream_t stream;
+    muca_dev_buffers d;
+    std::vector<int> order;   // position -> site
+    std::vector<double> lnW;  // current weights (V+1)
+    // launch shape
+    int wpw, bpl, lds_tables_req;
+    // pinned staging
+    unsigned char *pin_tables;  // Bp | R | lnW regions of the tables buffer
+    unsigned char *pin_hist;    // hist + error word
+    unsigned char *pin_obs;     // obs buffer
+    hipEvent_t ev_tables;
+    int64_t recorded;           // sweeps recorded into accum since the last clear
+};
+
+namespace {
+
+struct LaunchPlan {
+    bool lds_tables, lds_hist;
+    size_t lds;
+    int off_hist, off_lat, off_r, off_nb;
+};
+
+bool plan_launch(const muca_job *j, int wpw, int lds_tables_req, LaunchPlan *out)
+{
+    const Layout &g = j->g;
+    const int wpb = 4 / wpw;
+    auto build = [&](bool tables, bool hist, LaunchPlan *pl) {
+        size_t off = kLdsFixed;
+        pl->off_hist = (int)off;
+        if (hist) off += align_up(4 * ((size_t)g.V + 1), 16);
+        pl->off_lat = (int)off;
+        off += align_up((size_t)wpb * g.Vp, 16);
+        pl->off_r = (int)off;
+        if (tables) off += align_up(16 * ((size_t)g.V + 1), 16);
+        pl->off_nb = (int)off;
+        if (tables) off += align_up((size_t)12 * g.Vp, 16);
+        pl->lds = off;
+        pl->lds_tables = tables;
+        pl->lds_hist = hist;
+        return off <= (size_t)j->max_lds;
+    };
+    const bool try_tables[2] = {true, false};
+    for (bool t : try_tables) {
+        if (lds_tables_req == 1 && !t) continue;
+        if (lds_tables_req == 0 && t) continue;
+        if (build(t, true, out)) return true;
+        if (build(t, false, out)) return true;
+    }
+    return false;
+}
+
+void default_launch(muca_job *j)
+{
+    const int nw = j->p.n_walkers;
+    // Give each walker as many lanes as keeps about 1-2 waves per SIMD busy.
+    const int simds = 4 * (j->n_cu > 0 ? j->n_cu : 256);
+    int wpw = 1;
+    if (4 * nw <= 2 * simds)
+        wpw = 4;
+    else if (2 * nw <= 2 * simds)
+        wpw = 2;
+    // Blocks (4 sites) in the largest colour class vs lanes per walker.
+    int largest = 0;
+    for (int c = 0; c < j->g.C; ++c) largest = std::max(largest, j->g.cls[c + 1] - j->g.cls[c]);
+    const int blocks = (largest + 3) / 4 + 1;
+    int bpl = blocks > 64 * wpw ? 2 : 1;
+    LaunchPlan pl;
+    while (!plan_launch(j, wpw, -1, &pl) && wpw < 4) wpw *= 2;  // fewer walkers per block -> less LDS
+    j->wpw = wpw;
+    j->bpl = bpl;
+    j->lds_tables_req = -1;
+}
+
+int upload_tables(muca_job *j)
+{
+    const Layout &g = j->g;
+    HIP_TRY(hipEventSynchronize(j->ev_tables));  // staging free again
+    double *Bp = reinterpret_cast<double *>(j->pin_tables + g.off_bp);
+    double *R = reinterpret_cast<double *>(j->pin_tables + g.off_r);
+    double *lw = reinterpret_cast<double *>(j->pin_tables + g.off_lnw);
+    std::vector<double> Rp(g.V + 1), Rm(g.V + 1);
+    for (int k = 0; k < 32; ++k) Bp[k] = 0.0;
+    compute_tables(g.V, j->beta, j->lnW.data(), Bp, Rp.data(), Rm.data());
+    for (int E = 0; E <= g.V; ++E) {
+        R[2 * E] = Rm[E];
+        R[2 * E + 1] = Rp[E];
+    }
+    std::memcpy(lw, j->lnW.data(), sizeof(double) * (g.V + 1));
+    HIP_TRY(hipMemcpyAsync(j->d.tables, j->pin_tables, g.off_nb, hipMemcpyHostToDevice, j->stream));
+    HIP_TRY(hipEventRecord(j->ev_tables, j->stream));
+    return MUCA_OK;
+}
+
+int clear_accum(muca_job *j)
+{
+    HIP_TRY(launch_zero(j->d.accum, j->g.accum_bytes, j->stream));
+    j->recorded = 0;
+    return MUCA_OK;
+}
+
+int use_device(const muca_job *j)
+{
+    HIP_TRY(hipSetDevice(j->device));
+    return MUCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int muca_query_sizes(const muca_params *params, size_t *lattice_bytes, size_t *state_bytes,
+                     size_t *hist_bytes, size_t *tables_bytes, size_t *accum_bytes, size_t *obs_bytes)
+{
+    if (!params_ok(params)) return MUCA_E_INVAL;
+    const Layout g = make_layout(params);
+    if (lattice_bytes) *lattice_bytes = g.lattice_bytes;
+    if (state_bytes) *state_bytes = g.state_bytes;
+    if (hist_bytes) *hist_bytes = g.hist_bytes;
+    if (tables_bytes) *tables_bytes = g.tables_bytes;
+    if (accum_bytes) *accum_bytes = g.accum_bytes;
+    if (obs_bytes) *obs_bytes = g.obs_bytes;
+    return MUCA_OK;
+}
+
+int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const double *lnW_host,
+              void *stream, muca_job **out)
+{
+    if (!out) return MUCA_E_INVAL;
+    *out = nullptr;
+    if (!params_ok(params) || !buffers) return MUCA_E_INVAL;
+    void *ptrs[6] = {buffers->lattice, buffers->walker_state, buffers->hist,
+                     buffers->tables, buffers->accum, buffers->obs};
+    for (void *q : ptrs)
+        if (!q || (reinterpret_cast<uintptr_t>(q) & 255u)) return MUCA_E_INVAL;
+    const Layout g = make_layout(params);
+    if (lnW_host)
+        for (int E = 0; E <= g.V; ++E)
+            if (!std::isfinite(lnW_host[E])) return MUCA_E_INVAL;
+
+    muca_job *j = new (std::nothrow) muca_job();
+    if (!j) return MUCA_E_SIZE;
+    j->p = *params;
+    j->g = g;
+    build_order(g.L, j->order, j->g.cls);
+    j->beta = beta_of(params->T);
+    j->k0 = (uint32_t)(params->seed & 0xffffffffu);
+    j->k1 = (uint32_t)(params->seed >> 32);
+    j->stream = reinterpret_cast<hipStream_t>(stream);
+    j->d = *buffers;
+    if (lnW_host)
+        j->lnW.assign(lnW_host, lnW_host + g.V + 1);
+    else
+        j->lnW.assign(g.V + 1, 0.0);
+    j->recorded = 0;
+
+    auto bail = [&](int rc) {
+        muca_free(j);
+        return rc;
+    };
+    if (hipGetDevice(&j->device) != hipSuccess) return bail(fail_device(hipGetLastError(), "hipGetDevice"));
+    j->max_lds = query_max_lds(j->device);
+    if (hipDeviceGetAttribute(&j->n_cu, hipDeviceAttributeMultiprocessorCount, j->device) != hipSuccess)
+        j->n_cu = 256;
+    hipError_t e;
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&j->pin_tables), g.tables_bytes, hipHostMallocDefault)) != hipSuccess)
+        return bail(fail_device(e, "hipHostMalloc(tables)"));
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&j->pin_hist), g.hist_bytes, hipHostMallocDefault)) != hipSuccess)
+        return bail(fail_device(e, "hipHostMalloc(hist)"));
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&j->pin_obs), g.obs_bytes, hipHostMallocDefault)) != hipSuccess)
+        return bail(fail_device(e, "hipHostMalloc(obs)"));
+    if ((e = hipEventCreateWithFlags(&j->ev_tables, hipEventDisableTiming)) != hipSuccess)
+        return bail(fail_device(e, "hipEventCreate"));
+    if ((e = hipEventRecord(j->ev_tables, j->stream)) != hipSuccess) return bail(fail_device(e, "hipEventRecord"));
+
+    // neighbour and site tables in position space (uploaded once)
+    {
+        const int L = g.L, V = g.V, Vp = g.Vp;
+        std::vector<int> pos(V);
+        for (int p = 0; p < V; ++p) pos[j->order[p]] = p;
+        uint16_t *nb = reinterpret_cast<uint16_t *>(j->pin_tables + g.off_nb);
+        uint16_t *site = reinterpret_cast<uint16_t *>(j->pin_tables + g.off_site);
+        std::memset(nb, 0, (size_t)12 * Vp);
+        std::memset(site, 0, (size_t)2 * Vp);
+        for (int p = 0; p < V; ++p) {
+            const int i = j->order[p];
+            const int x = i % L, y = (i / L) % L, z = i / (L * L);
+            const int nbr[6] = {(x + 1) % L + L * (y + L * z), (x + L - 1) % L + L * (y + L * z),
+                                x + L * ((y + 1) % L + L * z), x + L * ((y + L - 1) % L + L * z),
+                                x + L * (y + L * ((z + 1) % L)), x + L * (y + L * ((z + L - 1) % L))};
+            for (int dir = 0; dir < 6; ++dir) nb[(size_t)dir * Vp + p] = (uint16_t)pos[nbr[dir]];
+            site[p] = (uint16_t)i;
+        }
+        unsigned char *dt = reinterpret_cast<unsigned char *>(j->d.tables);
+        if ((e = hipMemcpyAsync(dt + g.off_nb, j->pin_tables + g.off_nb, g.tables_bytes - g.off_nb,
+                                hipMemcpyHostToDevice, j->stream)) != hipSuccess)
+            return bail(fail_device(e, "hipMemcpyAsync(nb)"));
+        if ((e = hipStreamSynchronize(j->stream)) != hipSuccess)
+            return bail(fail_device(e, "hipStreamSynchronize"));
+    }
+    int rc = upload_tables(j);
+    if (rc) return bail(rc);
+    if ((e = launch_zero(j->d.hist, g.hist_bytes, j->stream)) != hipSuccess) return bail(fail_device(e, "zero hist"));
+    if ((e = launch_zero(j->d.accum, g.accum_bytes, j->stream)) != hipSuccess) return bail(fail_device(e, "zero accum"));
+    InitArgs ia;
+    ia.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
+    ia.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
+    ia.nb = reinterpret_cast<const uint16_t *>(reinterpret_cast<unsigned char *>(j->d.tables) + g.off_nb);
+    ia.site = reinterpret_cast<const uint16_t *>(reinterpret_cast<unsigned char *>(j->d.tables) + g.off_site);
+    ia.V = g.V;
+    ia.Vp = g.Vp;
+    ia.n_walkers = g.n_walkers;
+    ia.k0 = j->k0;
+    ia.k1 = j->k1;
+    if ((e = launch_init(ia, j->stream)) != hipSuccess) return bail(fail_device(e, "init kernels"));
+    if ((e = hipStreamSynchronize(j->stream)) != hipSuccess) return bail(fail_device(e, "hipStreamSynchronize"));
+    default_launch(j);
+    *out = j;
+    return MUCA_OK;
+}
+
+int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
+{
+    if (!j || n_sweeps < 0 || (flags & ~MUCA_RECORD)) return MUCA_E_INVAL;
+    if (n_sweeps > MUCA_MAX_SWEEPS_PER_CALL) return MUCA_E_OVERFLOW;
+    if (n_sweeps == 0) return MUCA_OK;
+    if (int rc = use_device(j)) return rc;
+    const Layout &g = j->g;
+    LaunchPlan pl;
+    if (!plan_launch(j, j->wpw, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
+    SweepArgs a;
+    a.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
+    a.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
+    a.hist = reinterpret_cast<unsigned long long *>(j->d.hist);
+    unsigned char *dt = reinterpret_cast<unsigned char *>(j->d.tables);
+    a.bp = reinterpret_cast<const double *>(dt + g.off_bp);
+    a.r = reinterpret_cast<const double *>(dt + g.off_r);
+    a.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
+    a.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
+    a.err = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256));
+    a.V = g.V;
+    a.Vp = g.Vp;
+    a.n_walkers = g.n_walkers;
+    a.n_classes = g.C;
+    for (int c = 0; c <= kMaxClasses; ++c) a.cls[c] = g.cls[c];
+    a.k0 = j->k0;
+    a.k1 = j->k1;
+    a.lds_hist = pl.lds_hist ? 1 : 0;
+    a.lds_off_hist = pl.off_hist;
+    a.lds_off_lat = pl.off_lat;
+    a.lds_off_r = pl.off_r;
+    a.lds_off_nb = pl.off_nb;
+    const bool record = (flags & MUCA_RECORD) != 0;
+    int64_t left = n_sweeps;
+    while (left > 0) {
+        const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
+        a.n_sweeps = chunk;
+        HIP_TRY(launch_sweep(a, j->wpw, j->bpl, record, pl.lds_tables, pl.lds, j->stream));
+        left -= chunk;
+    }
+    if (record) j->recorded += n_sweeps;
+    return MUCA_OK;
+}
+
+int muca_reduce_hist(muca_job *j, int64_t *hist_host, int32_t reset)
+{
+    if (!j || !hist_host) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    const Layout &g = j->g;
+    HIP_TRY(hipMemcpyAsync(j->pin_hist, j->d.hist, g.hist_bytes, hipMemcpyDeviceToHost, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    const int err = *reinterpret_cast<const int *>(j->pin_hist + align_up(8 * ((size_t)g.V + 1), 256));
+    std::memcpy(hist_host, j->pin_hist, 8 * ((size_t)g.V + 1));
+    if (reset) HIP_TRY(launch_zero(j->d.hist, align_up(8 * ((size_t)g.V + 1), 16), j->stream));
+    if (err) {
+        g_detail = "sweep kernel reported an internal error (fixed-point round cap)";
+        return MUCA_E_DEVICE;
+    }
+    return MUCA_OK;
+}
+
+int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, double *flatness_out)
+{
+    if (!j || !hist) return MUCA_E_INVAL;
+    const int V = j->g.V;
+    for (int E = 0; E <= V; ++E)
+        if (hist[E] < 0) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    // W <- W / H on the visited bins (plain multicanonical recursion)
+    int64_t sum = 0, least = hist[0];
+    for (int E = 0; E <= V; ++E) {
+        sum += hist[E];
+        least = std::min(least, hist[E]);
+        if (hist[E] > 0) j->lnW[E] = j->lnW[E] - std::log((double)hist[E]);
+    }
+    if (flatness_out) *flatness_out = sum > 0 ? (double)least / ((double)sum / (double)(V + 1)) : 0.0;
+    if (lnW_out) std::memcpy(lnW_out, j->lnW.data(), sizeof(double) * (V + 1));
+    if (int rc = upload_tables(j)) return rc;
+    return clear_accum(j);
+}
+
+int muca_set_weights(muca_job *j, const double *lnW)
+{
+    if (!j || !lnW) return MUCA_E_INVAL;
+    for (int E = 0; E <= j->g.V; ++E)
+        if (!std::isfinite(lnW[E])) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    j->lnW.assign(lnW, lnW + j->g.V + 1);
+    if (int rc = upload_tables(j)) return rc;
+    return clear_accum(j);
+}
+
+int muca_get_weights(const muca_job *j, double *lnW_out)
+{
+    if (!j || !lnW_out) return MUCA_E_INVAL;
+    std::memcpy(lnW_out, j->lnW.data(), sizeof(double) * (j->g.V + 1));
+    return MUCA_OK;
+}
+
+int muca_reweight(muca_job *j, const double *delta, int32_t n_delta, muca_obs *out)
+{
+    if (!j || !delta || !out || n_delta < 1) return MUCA_E_INVAL;
+    if (n_delta > j->g.max_delta) return MUCA_E_SIZE;
+    for (int k = 0; k < n_delta; ++k)
+        if (!std::isfinite(delta[k])) return MUCA_E_INVAL;
+    if (j->recorded <= 0) return MUCA_E_STATE;
+    if (int rc = use_device(j)) return rc;
+    const Layout &g = j->g;
+    double *pd = reinterpret_cast<double *>(j->pin_obs);
+    std::memcpy(pd, delta, sizeof(double) * n_delta);
+    double *dobs = reinterpret_cast<double *>(j->d.obs);
+    HIP_TRY(hipMemcpyAsync(dobs, pd, sizeof(double) * n_delta, hipMemcpyHostToDevice, j->stream));
+    ReweightArgs a;
+    a.acc = reinterpret_cast<const unsigned long long *>(j->d.accum);
+    a.lnw = reinterpret_cast<const double *>(reinterpret_cast<unsigned char *>(j->d.tables) + g.off_lnw);
+    a.delta = dobs;
+    a.obs = dobs + g.max_delta;
+    a.V = g.V;
+    a.beta = j->beta;
+    HIP_TRY(launch_reweight(a, n_delta, j->stream));
+    HIP_TRY(hipMemcpyAsync(pd + g.max_delta, dobs + g.max_delta, sizeof(double) * MUCA_N_OBS * n_delta,
+                           hipMemcpyDeviceToHost, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    std::memcpy(out, pd + g.max_delta, sizeof(double) * MUCA_N_OBS * n_delta);
+    return MUCA_OK;
+}
+
+int muca_read_state(muca_job *j, int8_t *spins, int64_t *state)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    const Layout &g = j->g;
+    std::vector<int8_t> lat;
+    std::vector<int32_t> st;
+    if (spins) {
+        lat.resize((size_t)g.n_walkers * g.Vp);
+        HIP_TRY(hipMemcpyAsync(lat.data(), j->d.lattice, lat.size(), hipMemcpyDeviceToHost, j->stream));
+    }
+    if (state) {
+        st.resize((size_t)g.n_walkers * 4);
+        HIP_TRY(hipMemcpyAsync(st.data(), j->d.walker_state, st.size() * 4, hipMemcpyDeviceToHost, j->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    for (int w = 0; spins && w < g.n_walkers; ++w)
+        for (int p = 0; p < g.V; ++p) spins[(size_t)w * g.V + j->order[p]] = lat[(size_t)w * g.Vp + p];
+    for (int w = 0; state && w < g.n_walkers; ++w) {
+        state[4 * (size_t)w + 0] = st[4 * (size_t)w + 0];
+        state[4 * (size_t)w + 1] = st[4 * (size_t)w + 1];
+        state[4 * (size_t)w + 2] = st[4 * (size_t)w + 2];
+        state[4 * (size_t)w + 3] = (int64_t)(uint32_t)st[4 * (size_t)w + 3];
+    }
+    return MUCA_OK;
+}
+
+int muca_write_state(muca_job *j, const int8_t *spins, const int64_t *state)
+{
+    if (!j || !spins || !state) return MUCA_E_INVAL;
+    const Layout &g = j->g;
+    for (size_t k = 0; k < (size_t)g.n_walkers * g.V; ++k)
+        if (spins[k] < -1 || spins[k] > 1) return MUCA_E_INVAL;
+    for (int w = 0; w < g.n_walkers; ++w) {
+        const int64_t *s = state + 4 * (size_t)w;
+        if (s[1] < 0 || s[1] > g.V || s[0] < -3LL * g.V || s[0] > 3LL * g.V || s[2] < -g.V || s[2] > g.V ||
+            s[3] < 0 || s[3] > 0xffffffffLL)
+            return MUCA_E_INVAL;
+    }
+    if (int rc = use_device(j)) return rc;
+    std::vector<int8_t> lat((size_t)g.n_walkers * g.Vp, 0);
+    std::vector<int32_t> st((size_t)g.n_walkers * 4);
+    for (int w = 0; w < g.n_walkers; ++w) {
+        for (int p = 0; p < g.V; ++p) lat[(size_t)w * g.Vp + p] = spins[(size_t)w * g.V + j->order[p]];
+        for (int k = 0; k < 4; ++k) st[4 * (size_t)w + k] = (int32_t)(uint32_t)state[4 * (size_t)w + k];
+    }
+    HIP_TRY(hipMemcpyAsync(j->d.lattice, lat.data(), lat.size(), hipMemcpyHostToDevice, j->stream));
+    HIP_TRY(hipMemcpyAsync(j->d.walker_state, st.data(), st.size() * 4, hipMemcpyHostToDevice, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    return MUCA_OK;
+}
+
+int muca_read_accum(muca_job *j, int64_t *sums, uint64_t *sm4)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    const size_t V1 = (size_t)j->g.V + 1;
+    std::vector<uint64_t> buf(7 * V1);
+    HIP_TRY(hipMemcpyAsync(buf.data(), j->d.accum, buf.size() * 8, hipMemcpyDeviceToHost, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    if (sums) std::memcpy(sums, buf.data(), 5 * V1 * 8);
+    if (sm4) std::memcpy(sm4, buf.data() + 5 * V1, 2 * V1 * 8);
+    return MUCA_OK;
+}
+
+int muca_reset_accum(muca_job *j)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    return clear_accum(j);
+}
+
+int muca_set_launch(muca_job *j, int32_t wpw, int32_t bpl, int32_t lds_tables)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (!(wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2) || lds_tables < -1 || lds_tables > 1)
+        return MUCA_E_INVAL;
+    LaunchPlan pl;
+    if (!plan_launch(j, wpw, lds_tables, &pl)) return MUCA_E_SIZE;
+    j->wpw = wpw;
+    j->bpl = bpl;
+    j->lds_tables_req = lds_tables;
+    return MUCA_OK;
+}
+
+int muca_get_launch(const muca_job *j, int32_t *wpw, int32_t *bpl, int32_t *lds_tables, int32_t *lds_bytes)
+{
+    if (!j) return MUCA_E_INVAL;
+    LaunchPlan pl;
+    if (!plan_launch(j, j->wpw, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
+    if (wpw) *wpw = j->wpw;
+    if (bpl) *bpl = j->bpl;
+    if (lds_tables) *lds_tables = pl.lds_tables ? 1 : 0;
+    if (lds_bytes) *lds_bytes = (int32_t)pl.lds;
+    return MUCA_OK;
+}
+
+int muca_host_tables(int32_t L, double T, const double *lnW, double *Bp, double *Rp, double *Rm)
+{
+    if (L < MUCA_L_MIN || L > MUCA_L_MAX || !(T > 0.0) || !lnW || !Bp || !Rp || !Rm) return MUCA_E_INVAL;
+    compute_tables(L * L * L, beta_of(T), lnW, Bp, Rp, Rm);
+    return MUCA_OK;
+}
+
+int muca_host_order(int32_t L, int32_t *order)
+{
+    if (L < MUCA_L_MIN || L > MUCA_L_MAX || !order) return MUCA_E_INVAL;
+    std::vector<int> o;
+    int cls[kMaxClasses + 1];
+    build_order(L, o, cls);
+    for (size_t p = 0; p < o.size(); ++p) order[p] = o[p];
+    return MUCA_OK;
+}
+
+const char *muca_strerror(int code)
+{
+    switch (code) {
+    case MUCA_OK: return "ok";
+    case MUCA_E_INVAL: return "invalid argument";
+    case MUCA_E_UNSUPPORTED: return "unsupported request";
+    case MUCA_E_SIZE: return "size limit exceeded";
+    case MUCA_E_STATE: return "call out of order (nothing recorded?)";
+    case MUCA_E_OVERFLOW: return "counter overflow";
+    case MUCA_E_DEVICE:
+        return g_detail.empty() ? "device error" : g_detail.c_str();
+    default: return "unknown error code";
+    }
+}
+
+void muca_free(muca_job *j)
+{
+    if (!j) return;
+    (void)hipSetDevice(j->device);
+    (void)hipStreamSynchronize(j->stream);
+    if (j->ev_tables) (void)hipEventDestroy(j->ev_tables);
+    if (j->pin_tables) (void)hipHostFree(j->pin_tables);
+    if (j->pin_hist) (void)hipHostFree(j->pin_hist);
+    if (j->pin_obs) (void)hipHostFree(j->pin_obs);
+    delete j;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Internal declarations shared by the host side (muca_host.cpp) and the device
+// kernels (muca_kernels.hip) of libmuca.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace muca {
+
+constexpr int kBlock = 256;          // threads per block of every kernel: 4 wave64
+constexpr int kMaxClasses = 3;       // colours of the visiting order
+constexpr int kLdsFixed = 384;       // B'[32] doubles + scan scratch at the start of LDS
+constexpr int kMaxSweepsPerLaunch = 1 << 26;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Everything that depends only on L: sizes of the device buffers and offsets of
+// the sub-tables inside the tables buffer.
+struct Layout {
+    int L, V, Vp, C;
+    int cls[kMaxClasses + 1];  // colour class c covers positions [cls[c], cls[c+1])
+    int n_walkers, max_delta;
+    size_t lattice_bytes, state_bytes, hist_bytes, tables_bytes, accum_bytes, obs_bytes;
+    size_t off_bp, off_r, off_lnw, off_nb, off_site;  // byte offsets inside tables
+};
+
+// Arguments of the sweep kernel.
+struct SweepArgs {
+    int8_t *lattice;               // n_walkers x Vp, colour-major positions
+    int32_t *wstate;               // n_walkers x 4: E_J, E_Delta, M, sweeps done
+    unsigned long long *hist;      // V+1
+    const double *bp;              // 25 (+pad) thresholds 2^31 exp(-beta k)
+    const double *r;               // (V+1) x 2: [E][0] = R_-, [E][1] = R_+
+    const uint16_t *nb;            // 6 x Vp neighbour positions
+    unsigned long long *acc;       // 7 x (V+1) production sums
+    int *err;                      // device error word (the tail of the hist buffer)
+    int V, Vp, n_walkers, n_classes;
+    int cls[kMaxClasses + 1];
+    uint32_t k0, k1;
+    int n_sweeps;
+    int lds_hist;                  // 1: histogram in LDS, flushed at the end
+    int lds_off_hist, lds_off_lat, lds_off_r, lds_off_nb;
+};
+
+struct InitArgs {
+    int8_t *lattice;
+    int32_t *wstate;
+    const uint16_t *nb;
+    const uint16_t *site;
+    int V, Vp, n_walkers;
+    uint32_t k0, k1;
+};
+
+struct ReweightArgs {
+    const unsigned long long *acc;  // 7 x (V+1)
+    const double *lnw;              // V+1
+    const double *delta;            // n_delta
+    double *obs;                    // n_delta x 15
+    int V;
+    double beta;
+};
+
+// Launchers (muca_kernels.hip).  Return the hipError_t of the launch.
+hipError_t launch_init(const InitArgs &a, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs &a, int waves_per_walker, int blocks_per_lane, bool record,
+                        bool lds_tables, size_t lds_bytes, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s);
+
+}  // namespace muca

@@ -1,0 +1,571 @@
+// Device kernels of libmuca for gfx950 (CDNA4, wave64).
+//
+// The sweep kernel runs the multicanonical Markov chain of the Blume-Capel model
+// (Sec. II of the paper: single-site Metropolis under exp(-beta E_J) W(E_Delta))
+// with several lanes cooperating on one walker without changing the chain:
+//
+//  * Sites are visited in colour-major order.  Inside one colour class no two
+//    sites are neighbours, so every lane can evaluate its sites' neighbour sums,
+//    proposals, Philox words and E_J changes at once.
+//  * The only sequential coupling inside a class is E_Delta: the acceptance of
+//    a move that creates or removes a vacancy reads W at the walker's current
+//    E_Delta.  It is resolved exactly by a fixed-point iteration: each site
+//    guesses the E_Delta it will see, decides, a walker-wide prefix sum of the
+//    accepted E_Delta steps gives new guesses, and the loop stops when no guess
+//    changes.  Iteration k fixes at least the first k sites of the chain, so it
+//    ends after at most (sites in the pass + 1) rounds; in practice 2-4.
+//  * Lattices live in LDS as one int8 per site in colour-major position order;
+//    a lane owns 4 consecutive positions (one Philox block) per group, so spin
+//    writes are whole dwords with no atomics.  Thresholds B', R_+-, and the
+//    neighbour table sit in LDS when they fit, else are read through L1/L2.
+//  * Histograms: one LDS atomic per walker per sweep, flushed to HBM with one
+//    64-bit atomic per nonzero bin at the end of the launch.
+#include <hip/hip_runtime.h>
+
+#include "muca_internal.h"
+#include "muca_philox.h"
+
+namespace muca {
+
+// ---------------------------------------------------------------------------
+// Wave64 cross-lane helpers (DPP row shifts and row broadcasts of GFX9).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned wave_incl_sum(unsigned x)
+{
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ unsigned wave_total(unsigned incl)
+{
+    return (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Proposal: the b-th (ascending) of the two spin values other than s.
+__device__ __forceinline__ int propose(int s, int b)
+{
+    return b ? (s == 1 ? 0 : 1) : (s == -1 ? 0 : -1);
+}
+
+// ---------------------------------------------------------------------------
+// Sweep kernel.
+//   WPW: waves per walker (1, 2, 4); BPL: Philox blocks (4 sites) per lane per
+//   group; RECORD: accumulate production sums; LDS_TABLES: R and neighbour
+//   table staged in LDS.
+// ---------------------------------------------------------------------------
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES>
+__global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
+{
+    constexpr int WPB = 4 / WPW;   // walkers per block
+    constexpr int GL = 64 * WPW;   // lanes per walker
+    constexpr int NS = 4 * BPL;    // sites per lane per group
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sBp = reinterpret_cast<double *>(smem);
+    int *sTot = reinterpret_cast<int *>(smem + 256);  // [4] wave totals
+    int *sFlag = sTot + 4;                             // [4] wave "changed" flags
+    unsigned *sRed = reinterpret_cast<unsigned *>(sTot + 8);  // [8] per-wave E_J / M sums
+    unsigned *sHist = reinterpret_cast<unsigned *>(smem + a.lds_off_hist);
+    int8_t *sLat = reinterpret_cast<int8_t *>(smem + a.lds_off_lat);
+
+    const int V = a.V, Vp = a.Vp;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int slot = wave / WPW, wi = wave % WPW;
+    const int lg = wi * 64 + lane;
+    const int walker = blockIdx.x * WPB + slot;
+    const bool live = walker < a.n_walkers;
+
+    // ---- stage tables and lattices in LDS ----
+    for (int k = tid; k < 32; k += kBlock) sBp[k] = (k < 25) ? a.bp[k] : 0.0;
+    if (a.lds_hist)
+        for (int e = tid; e <= V; e += kBlock) sHist[e] = 0u;
+    const double *R = a.r;
+    const uint16_t *NB = a.nb;
+    if (LDS_TABLES) {
+        double *sR = reinterpret_cast<double *>(smem + a.lds_off_r);
+        uint16_t *sNB = reinterpret_cast<uint16_t *>(smem + a.lds_off_nb);
+        const int nr = 2 * (V + 1);
+        for (int k = tid; k < nr; k += kBlock) sR[k] = a.r[k];
+        const uint4 *gnb = reinterpret_cast<const uint4 *>(a.nb);
+        uint4 *lnb = reinterpret_cast<uint4 *>(sNB);
+        const int nq = (6 * Vp * 2) / 16;
+        for (int k = tid; k < nq; k += kBlock) lnb[k] = gnb[k];
+        R = sR;
+        NB = sNB;
+    }
+    int8_t *lat = sLat + (size_t)slot * Vp;
+    {
+        uint4 *dst = reinterpret_cast<uint4 *>(lat);
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.lattice + (size_t)(live ? walker : 0) * Vp);
+        for (int k = lg; k < Vp / 16; k += GL) dst[k] = live ? src[k] : make_uint4(0, 0, 0, 0);
+    }
+    int ED = 0, EJ0 = 0, M0 = 0;
+    uint32_t sweep = 0;
+    if (live) {
+        const int4 st = reinterpret_cast<const int4 *>(a.wstate)[walker];
+        EJ0 = st.x; ED = st.y; M0 = st.z; sweep = (uint32_t)st.w;
+    }
+    __syncthreads();
+
+    const uint32_t w32 = (uint32_t)walker;
+    unsigned myEJ = 0u, myM = 0u;  // this lane's accepted E_J and M changes (mod 2^32)
+    const int cap = GL * NS + 2;   // the fixed point is reached in <= GL*NS + 1 rounds
+
+    for (int n = 0; n < a.n_sweeps; ++n) {
+        for (int c = 0; c < a.n_classes; ++c) {
+            const int P0 = a.cls[c], P1 = a.cls[c + 1];
+            const int j0 = P0 >> 2, j1 = ((P1 - 1) >> 2) + 1;
+            for (int jbase = j0; jbase < j1; jbase += GL * BPL) {
+                const int jb0 = jbase + lg * BPL;
+                // ---- independent part: Philox, neighbour sums, proposals ----
+                double u[NS], bp[NS];
+                int dd[NS], dej[NS], dsg[NS], snew[NS], sold[NS];
+                bool valid[NS], acc0[NS];
+#pragma unroll
+                for (int q = 0; q < BPL; ++q) {
+                    const int jb = jb0 + q;
+                    const bool blk = jb < j1;
+                    const int jbc = blk ? jb : j0;
+                    const Ctr4 x = philox10((uint32_t)jbc, w32, sweep, 0u, a.k0, a.k1);
+                    const int word = *reinterpret_cast<const int *>(lat + 4 * jbc);
+                    int h[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int dir = 0; dir < 6; ++dir) {
+                        const uint2 nq = *reinterpret_cast<const uint2 *>(NB + dir * Vp + 4 * jbc);
+                        h[0] += lat[nq.x & 0xffffu];
+                        h[1] += lat[nq.x >> 16];
+                        h[2] += lat[nq.y & 0xffffu];
+                        h[3] += lat[nq.y >> 16];
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int k = 4 * q + t;
+                        const int p = 4 * jbc + t;
+                        valid[k] = blk && p >= P0 && p < P1;
+                        const int s = (int)(int8_t)(word >> (8 * t));
+                        const uint32_t xw = x.v[t];
+                        const int sn = propose(s, (int)(xw & 1u));
+                        u[k] = (double)(xw >> 1);
+                        sold[k] = s;
+                        snew[k] = sn;
+                        dsg[k] = sn - s;
+                        dej[k] = -(sn - s) * h[t];
+                        dd[k] = sn * sn - s * s;
+                        bp[k] = sBp[dej[k] + 12];
+                        acc0[k] = u[k] < bp[k];
+                    }
+                }
+                // ---- sequential part: exact fixed point over E_Delta ----
+                int Eg[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) Eg[k] = ED;
+                bool acc[NS];
+                int total = 0;
+                for (int it = 0;; ++it) {
+                    int ex[NS];
+                    int run = 0;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) {
+                        bool ac = acc0[k];
+                        if (dd[k] != 0) {
+                            const int e = min(max(Eg[k], 0), V);
+                            ac = u[k] < bp[k] * R[2 * e + (dd[k] > 0 ? 1 : 0)];
+                        }
+                        acc[k] = ac && valid[k];
+                        ex[k] = run;
+                        run += acc[k] ? dd[k] : 0;
+                    }
+                    const unsigned incl = wave_incl_sum((unsigned)run);
+                    const int laneOff = (int)incl - run;
+                    int waveOff = 0;
+                    int wtotal = (int)wave_total(incl);
+                    if (WPW > 1) {
+                        if (lane == 63) sTot[wave] = wtotal;
+                        __syncthreads();
+                        int sum = 0, before = 0;
+#pragma unroll
+                        for (int v = 0; v < WPW; ++v) {
+                            const int tv = sTot[slot * WPW + v];
+                            before += (v < wi) ? tv : 0;
+                            sum += tv;
+                        }
+                        waveOff = before;
+                        wtotal = sum;
+                    }
+                    bool changed = false;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) {
+                        const int ne = ED + waveOff + laneOff + ex[k];
+                        changed |= valid[k] && dd[k] != 0 && ne != Eg[k];
+                        Eg[k] = ne;
+                    }
+                    bool any = __ballot(changed) != 0ull;
+                    if (WPW > 1) {
+                        if (lane == 0) sFlag[wave] = any ? 1 : 0;
+                        __syncthreads();
+                        any = (sFlag[0] | sFlag[1] | sFlag[2] | sFlag[3]) != 0;
+                    }
+                    if (!any || it >= cap) {
+                        if (any && lane == 0) atomicOr(a.err, 1);
+                        total = wtotal;
+                        break;
+                    }
+                }
+                // ---- apply the accepted moves ----
+#pragma unroll
+                for (int q = 0; q < BPL; ++q) {
+                    const int jb = jb0 + q;
+                    unsigned nw = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int k = 4 * q + t;
+                        const int v = acc[k] ? snew[k] : sold[k];
+                        nw |= ((unsigned)v & 0xffu) << (8 * t);
+                        myEJ += acc[k] ? (unsigned)dej[k] : 0u;
+                        myM += acc[k] ? (unsigned)dsg[k] : 0u;
+                    }
+                    if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
+                }
+                ED += total;
+            }
+            if (WPW > 1)
+                __syncthreads();
+            else
+                wave_sync_lds();
+        }
+        sweep += 1u;
+        // ---- measurement after the sweep ----
+        if (RECORD) {
+            unsigned ej = wave_total(wave_incl_sum(myEJ));
+            unsigned m = wave_total(wave_incl_sum(myM));
+            if (WPW > 1) {
+                if (lane == 0) {
+                    sRed[2 * wave] = ej;
+                    sRed[2 * wave + 1] = m;
+                }
+                __syncthreads();
+                ej = 0u;
+                m = 0u;
+#pragma unroll
+                for (int v = 0; v < WPW; ++v) {
+                    ej += sRed[2 * (slot * WPW + v)];
+                    m += sRed[2 * (slot * WPW + v) + 1];
+                }
+            }
+            if (live && lg == 0) {
+                const long long EJ = (long long)(int)((unsigned)EJ0 + ej);
+                const long long M = (long long)(int)((unsigned)M0 + m);
+                const int V1 = V + 1;
+                unsigned long long *acc = a.acc;
+                const unsigned long long m2 = (unsigned long long)(M * M);
+                const unsigned long long m4 = m2 * m2;
+                atomicAdd(&acc[0 * V1 + ED], 1ull);
+                atomicAdd(&acc[1 * V1 + ED], (unsigned long long)EJ);
+                atomicAdd(&acc[2 * V1 + ED], (unsigned long long)(EJ * EJ));
+                atomicAdd(&acc[3 * V1 + ED], (unsigned long long)(M < 0 ? -M : M));
+                atomicAdd(&acc[4 * V1 + ED], m2);
+                const unsigned long long old = atomicAdd(&acc[5 * V1 + ED], m4);
+                if (old + m4 < old) atomicAdd(&acc[6 * V1 + ED], 1ull);
+            }
+        }
+        if (live && lg == 0) {
+            if (a.lds_hist)
+                atomicAdd(&sHist[ED], 1u);
+            else
+                atomicAdd(&a.hist[ED], 1ull);
+        }
+    }
+
+    // ---- write back ----
+    unsigned ej = wave_total(wave_incl_sum(myEJ));
+    unsigned m = wave_total(wave_incl_sum(myM));
+    __syncthreads();  // every wave is done with sRed and sHist of the last sweep
+    if (lane == 0) {
+        sRed[2 * wave] = ej;
+        sRed[2 * wave + 1] = m;
+    }
+    __syncthreads();
+    ej = 0u;
+    m = 0u;
+#pragma unroll
+    for (int v = 0; v < WPW; ++v) {
+        ej += sRed[2 * (slot * WPW + v)];
+        m += sRed[2 * (slot * WPW + v) + 1];
+    }
+    if (live) {
+        uint4 *dst = reinterpret_cast<uint4 *>(a.lattice + (size_t)walker * Vp);
+        const uint4 *src = reinterpret_cast<const uint4 *>(lat);
+        for (int k = lg; k < Vp / 16; k += GL) dst[k] = src[k];
+        if (lg == 0)
+            reinterpret_cast<int4 *>(a.wstate)[walker] =
+                make_int4((int)((unsigned)EJ0 + ej), ED, (int)((unsigned)M0 + m), (int)sweep);
+    }
+    if (a.lds_hist)
+        for (int e = tid; e <= V; e += kBlock) {
+            const unsigned cnt = sHist[e];
+            if (cnt) atomicAdd(&a.hist[e], (unsigned long long)cnt);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Initial lattices: spin at position p (site i = site[p]) from word i&3 of the
+// Philox block (i>>2, w, 0, 1): s = floor(3 x / 2^32) - 1.  Padding bytes are 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void muca_init_lattice_kernel(InitArgs a)
+{
+    const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (size_t)a.n_walkers * a.Vp) return;
+    const int w = (int)(idx / (size_t)a.Vp);
+    const int p = (int)(idx % (size_t)a.Vp);
+    int v = 0;
+    if (p < a.V) {
+        const int i = a.site[p];
+        const Ctr4 x = philox10((uint32_t)(i >> 2), (uint32_t)w, 0u, 1u, a.k0, a.k1);
+        const uint32_t xw = x.v[i & 3];
+        v = (int)(((uint64_t)xw * 3u) >> 32) - 1;
+    }
+    a.lattice[idx] = (int8_t)v;
+}
+
+// E_J = -(1/2) sum_p s_p h_p (each bond twice), E_Delta = sum s^2, M = sum s.
+__global__ __launch_bounds__(kBlock) void muca_init_energy_kernel(InitArgs a)
+{
+    __shared__ int red[3][kBlock];
+    const int w = blockIdx.x;
+    const int8_t *lat = a.lattice + (size_t)w * a.Vp;
+    int sh = 0, s2 = 0, s1 = 0;
+    for (int p = threadIdx.x; p < a.V; p += kBlock) {
+        const int s = lat[p];
+        int h = 0;
+        for (int dir = 0; dir < 6; ++dir) h += lat[a.nb[dir * a.Vp + p]];
+        sh += s * h;
+        s2 += s * s;
+        s1 += s;
+    }
+    red[0][threadIdx.x] = sh;
+    red[1][threadIdx.x] = s2;
+    red[2][threadIdx.x] = s1;
+    __syncthreads();
+    for (int half = kBlock / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        reinterpret_cast<int4 *>(a.wstate)[w] = make_int4(-red[0][0] / 2, red[1][0], red[2][0], 0);
+}
+
+__global__ __launch_bounds__(kBlock) void muca_zero_kernel(uint4 *p, size_t n16)
+{
+    for (size_t k = blockIdx.x * (size_t)kBlock + threadIdx.x; k < n16; k += (size_t)gridDim.x * kBlock)
+        p[k] = make_uint4(0, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Reweighting, one block per Delta (Sec. II time-series reweighting grouped per
+// E_Delta bin; Eqs. (FieldDerivative), (sph)).  Fixed-order block reductions in
+// FP64; within-bin variances from exact 128-bit integers.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[kBlock])
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int half = kBlock / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half)
+#pragma unroll
+            for (int k = 0; k < N; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + half];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = sh[k][0];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double u128_to_double(unsigned long long hi, unsigned long long lo)
+{
+    return (double)hi * 18446744073709551616.0 + (double)lo;
+}
+
+__global__ __launch_bounds__(kBlock) void muca_reweight_kernel(ReweightArgs a)
+{
+    __shared__ double sh[8][kBlock];
+    __shared__ int shi[2][kBlock];
+    const int V = a.V, V1 = V + 1;
+    const unsigned long long *H = a.acc;
+    const long long *SJ = reinterpret_cast<const long long *>(a.acc + V1);
+    const long long *SJJ = reinterpret_cast<const long long *>(a.acc + 2 * V1);
+    const unsigned long long *SA = a.acc + 3 * V1;
+    const unsigned long long *SM2 = a.acc + 4 * V1;
+    const unsigned long long *SM4lo = a.acc + 5 * V1;
+    const unsigned long long *SM4hi = a.acc + 6 * V1;
+    const double delta = a.delta[blockIdx.x];
+    const double bd = a.beta * delta;
+
+    // pass 1: max exponent, first and last visited bin
+    double amax = -INFINITY;
+    int first = V1, last = -1;
+    for (int e = threadIdx.x; e <= V; e += kBlock)
+        if (H[e] > 0) {
+            amax = fmax(amax, -bd * (double)e - a.lnw[e]);
+            first = min(first, e);
+            last = max(last, e);
+        }
+    sh[0][threadIdx.x] = amax;
+    shi[0][threadIdx.x] = first;
+    shi[1][threadIdx.x] = last;
+    __syncthreads();
+    for (int half = kBlock / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) {
+            sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + half]);
+            shi[0][threadIdx.x] = min(shi[0][threadIdx.x], shi[0][threadIdx.x + half]);
+            shi[1][threadIdx.x] = max(shi[1][threadIdx.x], shi[1][threadIdx.x + half]);
+        }
+        __syncthreads();
+    }
+    amax = sh[0][0];
+    first = shi[0][0];
+    last = shi[1][0];
+    __syncthreads();
+
+    // pass 2: normalisation and first moments
+    double s1[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // Z, SJ, E, SJJ, SA, SM2, SM4, edge
+    for (int e = threadIdx.x; e <= V; e += kBlock) {
+        const unsigned long long h = H[e];
+        if (h == 0) continue;
+        const double w = exp(-bd * (double)e - a.lnw[e] - amax);
+        const double hw = w * (double)h;
+        s1[0] += hw;
+        s1[1] += w * (double)SJ[e];
+        s1[2] += hw * (double)e;
+        s1[3] += w * (double)SJJ[e];
+        s1[4] += w * (double)SA[e];
+        s1[5] += w * (double)SM2[e];
+        s1[6] += w * u128_to_double(SM4hi[e], SM4lo[e]);
+        if (e == first || e == last) s1[7] += hw;
+    }
+    block_sum<8>(s1, sh);
+    const double Z = s1[0];
+    const double eJ = s1[1] / Z, eD = s1[2] / Z, eJJ = s1[3] / Z;
+    const double eA = s1[4] / Z, eM2 = s1[5] / Z, eM4 = s1[6] / Z, edge = s1[7] / Z;
+
+    // pass 3: central moments (between-bin + exact within-bin variance)
+    double s2[4] = {0, 0, 0, 0};  // var_EJ, var_ED, cov, third
+    for (int e = threadIdx.x; e <= V; e += kBlock) {
+        const unsigned long long h = H[e];
+        if (h == 0) continue;
+        const double w = exp(-bd * (double)e - a.lnw[e] - amax);
+        const double hw = w * (double)h;
+        const double hd = (double)h;
+        const double mJ = (double)SJ[e] / hd;
+        const __int128 num = (__int128)(long long)h * (__int128)SJJ[e] - (__int128)SJ[e] * (__int128)SJ[e];
+        const double within = (double)num / (hd * hd);
+        const double dJ = mJ - eJ, dD = (double)e - eD;
+        s2[0] += hw * (within + dJ * dJ);
+        s2[1] += hw * dD * dD;
+        s2[2] += hw * dJ * dD;
+        s2[3] += hw * dJ * dD * dD;
+    }
+    block_sum<4>(s2, sh);
+    if (threadIdx.x == 0) {
+        const double beta = a.beta;
+        const double varJ = s2[0] / Z, varD = s2[1] / Z, cov = s2[2] / Z, third = s2[3] / Z;
+        const double varE = varJ + 2.0 * delta * cov + delta * delta * varD;
+        double *o = a.obs + (size_t)blockIdx.x * 15;
+        o[0] = delta;
+        o[1] = eJ;
+        o[2] = eD;
+        o[3] = eJ + delta * eD;
+        o[4] = eJJ;
+        o[5] = varJ;
+        o[6] = varD;
+        o[7] = -beta * cov;
+        o[8] = beta * beta * third;
+        o[9] = beta * beta * varE / (double)V;
+        o[10] = eA;
+        o[11] = eM2;
+        o[12] = eM4;
+        o[13] = eM2 > 0.0 ? 1.0 - eM4 / (3.0 * eM2 * eM2) : __builtin_nan("");
+        o[14] = edge;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_init(const InitArgs &a, hipStream_t s)
+{
+    const size_t n = (size_t)a.n_walkers * a.Vp;
+    hipLaunchKernelGGL(muca_init_lattice_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(muca_init_energy_kernel, dim3((unsigned)a.n_walkers), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    size_t blocks = (n16 + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(muca_zero_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint4 *>(p), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s)
+{
+    hipLaunchKernelGGL(muca_reweight_kernel, dim3((unsigned)n_delta), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES>
+static hipError_t launch_sweep_t(const SweepArgs &a, size_t lds, hipStream_t s)
+{
+    auto kern = muca_sweep_kernel<WPW, BPL, RECORD, LDS_TABLES>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    constexpr int WPB = 4 / WPW;
+    const unsigned blocks = (unsigned)((a.n_walkers + WPB - 1) / WPB);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int WPW, int BPL>
+static hipError_t launch_sweep_b(const SweepArgs &a, bool record, bool lds_tables, size_t lds, hipStream_t s)
+{
+    if (record)
+        return lds_tables ? launch_sweep_t<WPW, BPL, true, true>(a, lds, s)
+                          : launch_sweep_t<WPW, BPL, true, false>(a, lds, s);
+    return lds_tables ? launch_sweep_t<WPW, BPL, false, true>(a, lds, s)
+                      : launch_sweep_t<WPW, BPL, false, false>(a, lds, s);
+}
+
+hipError_t launch_sweep(const SweepArgs &a, int wpw, int bpl, bool record, bool lds_tables, size_t lds,
+                        hipStream_t s)
+{
+    if (wpw == 1) return bpl == 1 ? launch_sweep_b<1, 1>(a, record, lds_tables, lds, s)
+                                  : launch_sweep_b<1, 2>(a, record, lds_tables, lds, s);
+    if (wpw == 2) return bpl == 1 ? launch_sweep_b<2, 1>(a, record, lds_tables, lds, s)
+                                  : launch_sweep_b<2, 2>(a, record, lds_tables, lds, s);
+    return bpl == 1 ? launch_sweep_b<4, 1>(a, record, lds_tables, lds, s)
+                    : launch_sweep_b<4, 2>(a, record, lds_tables, lds, s);
+}
+
+}  // namespace muca

@@ -1,0 +1,41 @@
+// Philox4x32-10 counter-based generator for the device, from its published
+// definition (J. K. Salmon, M. A. Moraes, R. O. Dror, D. E. Shaw, "Parallel
+// random numbers: as easy as 1, 2, 3", SC'11): ten rounds; each round forms the
+// two 64-bit products of counter words 0 and 2 with the round multipliers,
+// mixes their high halves with counter words 1 and 3 and the round key, and the
+// key advances by the Weyl constants between rounds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace muca {
+
+struct Ctr4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Ctr4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t key0, uint32_t key1)
+{
+    constexpr uint32_t mulA = 0xD2511F53u, mulB = 0xCD9E8D57u;
+    constexpr uint32_t weylA = 0x9E3779B9u, weylB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t ka = key0 + weylA * (uint32_t)round;
+        const uint32_t kb = key1 + weylB * (uint32_t)round;
+        const uint64_t pa = (uint64_t)mulA * c0;
+        const uint64_t pb = (uint64_t)mulB * c2;
+        const uint32_t t0 = (uint32_t)(pb >> 32) ^ c1 ^ ka;
+        const uint32_t t2 = (uint32_t)(pa >> 32) ^ c3 ^ kb;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = t0;
+        c2 = t2;
+    }
+    Ctr4 r;
+    r.v[0] = c0; r.v[1] = c1; r.v[2] = c2; r.v[3] = c3;
+    return r;
+}
+
+}  // namespace muca

@@ -1,0 +1,247 @@
+"""ctypes binding of libmuca (include/muca.h): same names, argument marshalling only.
+
+PyTorch supplies the device memory (uint8 tensors sized by muca_query_sizes)
+and the HIP stream; every step of the method runs in libmuca's kernels and host
+code.  The binding fails loudly when libmuca.so is missing: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmuca.so")
+
+MUCA_OK = 0
+MUCA_RECORD = 1
+OBS_FIELDS = (
+    "delta", "mean_EJ", "mean_ED", "mean_E", "mean_EJ2", "var_EJ", "var_ED",
+    "C_field", "dC_dDelta", "cV", "mean_absM", "mean_M2", "mean_M4", "binder_U4",
+    "edge_weight",
+)
+EXPORTS = (
+    "muca_query_sizes", "muca_init", "muca_sweep", "muca_reduce_hist", "muca_update_weights",
+    "muca_set_weights", "muca_get_weights", "muca_reweight", "muca_read_state", "muca_write_state",
+    "muca_read_accum", "muca_reset_accum", "muca_set_launch", "muca_get_launch", "muca_host_tables",
+    "muca_host_order", "muca_strerror", "muca_free",
+)
+
+
+class MucaError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().muca_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: error {code}: {msg}")
+
+
+class muca_params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("T", ctypes.c_double), ("n_walkers", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("max_delta", ctypes.c_int32)]
+
+
+class muca_dev_buffers(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_void_p), ("walker_state", ctypes.c_void_p), ("hist", ctypes.c_void_p),
+                ("tables", ctypes.c_void_p), ("accum", ctypes.c_void_p), ("obs", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmuca.so (built by __graft_entry__.build()); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmuca.so not found at {LIB_PATH}: run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    P, vp, i32, i64, u32, dbl = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    sz = P(ctypes.c_size_t)
+    L.muca_query_sizes.argtypes = [P(muca_params), sz, sz, sz, sz, sz, sz]
+    L.muca_init.argtypes = [P(muca_params), P(muca_dev_buffers), P(dbl), vp, P(vp)]
+    L.muca_sweep.argtypes = [vp, i64, u32]
+    L.muca_reduce_hist.argtypes = [vp, P(i64), i32]
+    L.muca_update_weights.argtypes = [vp, P(i64), P(dbl), P(dbl)]
+    L.muca_set_weights.argtypes = [vp, P(dbl)]
+    L.muca_get_weights.argtypes = [vp, P(dbl)]
+    L.muca_reweight.argtypes = [vp, P(dbl), i32, P(dbl)]
+    L.muca_read_state.argtypes = [vp, P(ctypes.c_int8), P(i64)]
+    L.muca_write_state.argtypes = [vp, P(ctypes.c_int8), P(i64)]
+    L.muca_read_accum.argtypes = [vp, P(i64), P(ctypes.c_uint64)]
+    L.muca_reset_accum.argtypes = [vp]
+    L.muca_set_launch.argtypes = [vp, i32, i32, i32]
+    L.muca_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    L.muca_host_tables.argtypes = [i32, dbl, P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.muca_host_order.argtypes = [i32, P(i32)]
+    L.muca_strerror.argtypes = [ctypes.c_int]
+    L.muca_strerror.restype = ctypes.c_char_p
+    L.muca_free.argtypes = [vp]
+    L.muca_free.restype = None
+    for name in EXPORTS:
+        if name not in ("muca_strerror", "muca_free"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != MUCA_OK:
+        raise MucaError(rc, where)
+
+
+def _p(a: np.ndarray, ct):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _params(L, T, n_walkers, seed, max_delta) -> muca_params:
+    return muca_params(int(L), float(T), int(n_walkers), int(seed) & 0xFFFFFFFFFFFFFFFF, int(max_delta))
+
+
+def muca_query_sizes(L: int, T: float, n_walkers: int, seed: int = 0, max_delta: int = 0) -> dict:
+    s = [ctypes.c_size_t() for _ in range(6)]
+    pr = _params(L, T, n_walkers, seed, max_delta)
+    _check(lib().muca_query_sizes(ctypes.byref(pr), *[ctypes.byref(x) for x in s]), "muca_query_sizes")
+    return dict(zip(("lattice", "walker_state", "hist", "tables", "accum", "obs"), [x.value for x in s]))
+
+
+def muca_host_tables(L: int, T: float, lnW: np.ndarray):
+    V = L ** 3
+    lw = np.ascontiguousarray(lnW, dtype=np.float64)
+    Bp, Rp, Rm = np.zeros(25), np.zeros(V + 1), np.zeros(V + 1)
+    D = ctypes.c_double
+    _check(lib().muca_host_tables(L, float(T), _p(lw, D), _p(Bp, D), _p(Rp, D), _p(Rm, D)), "muca_host_tables")
+    return Bp, Rp, Rm
+
+
+def muca_host_order(L: int) -> np.ndarray:
+    o = np.zeros(L ** 3, dtype=np.int32)
+    _check(lib().muca_host_order(L, _p(o, ctypes.c_int32)), "muca_host_order")
+    return o
+
+
+class MucaJob:
+    """One multicanonical job (one (L, T), n_walkers walkers, one weight function).
+
+    Device buffers are torch uint8 tensors on `device`; work is ordered on
+    `stream` (a torch.cuda.Stream, default: the device's current stream)."""
+
+    def __init__(self, L: int, T: float, n_walkers: int, seed: int = 0, lnW: Optional[Sequence[float]] = None,
+                 max_delta: int = 256, device=None, stream=None):
+        import torch
+
+        self.L, self.V, self.T = int(L), int(L) ** 3, float(T)
+        self.beta = 0.0 if math.isinf(self.T) else 1.0 / self.T
+        self.n_walkers, self.seed, self.max_delta = int(n_walkers), int(seed), int(max_delta)
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        sizes = muca_query_sizes(L, T, n_walkers, seed, max_delta)
+        self.sizes = sizes
+        self._tensors = {}
+        ptrs = {}
+        for name, nbytes in sizes.items():
+            t = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-t.data_ptr()) % 256
+            self._tensors[name] = t
+            ptrs[name] = t.data_ptr() + off
+        self.buffers = muca_dev_buffers(**ptrs)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        pr = _params(L, T, n_walkers, seed, max_delta)
+        lw = None
+        if lnW is not None:
+            lw = np.ascontiguousarray(lnW, dtype=np.float64)
+            assert lw.shape == (self.V + 1,)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib().muca_init(ctypes.byref(pr), ctypes.byref(self.buffers),
+                                 _p(lw, ctypes.c_double) if lw is not None else None,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
+        _check(rc, "muca_init")
+        self._h = handle
+
+    # -- the hot path -----------------------------------------------------
+    def sweep(self, n_sweeps: int, record: bool = False):
+        _check(lib().muca_sweep(self._h, int(n_sweeps), MUCA_RECORD if record else 0), "muca_sweep")
+
+    def reduce_hist(self, reset: bool = True) -> np.ndarray:
+        h = np.zeros(self.V + 1, dtype=np.int64)
+        _check(lib().muca_reduce_hist(self._h, _p(h, ctypes.c_int64), 1 if reset else 0), "muca_reduce_hist")
+        return h
+
+    def update_weights(self, hist: np.ndarray) -> float:
+        h = np.ascontiguousarray(hist, dtype=np.int64)
+        flat = ctypes.c_double()
+        _check(lib().muca_update_weights(self._h, _p(h, ctypes.c_int64), None, ctypes.byref(flat)),
+               "muca_update_weights")
+        return flat.value
+
+    def reweight(self, deltas) -> np.ndarray:
+        d = np.ascontiguousarray(deltas, dtype=np.float64)
+        out = np.zeros((len(d), len(OBS_FIELDS)))
+        _check(lib().muca_reweight(self._h, _p(d, ctypes.c_double), len(d), _p(out, ctypes.c_double)),
+               "muca_reweight")
+        return out
+
+    # -- weights, state, accumulators ---------------------------------------
+    @property
+    def lnW(self) -> np.ndarray:
+        w = np.zeros(self.V + 1)
+        _check(lib().muca_get_weights(self._h, _p(w, ctypes.c_double)), "muca_get_weights")
+        return w
+
+    def set_weights(self, lnW):
+        w = np.ascontiguousarray(lnW, dtype=np.float64)
+        assert w.shape == (self.V + 1,)
+        _check(lib().muca_set_weights(self._h, _p(w, ctypes.c_double)), "muca_set_weights")
+
+    def read_state(self):
+        spins = np.zeros((self.n_walkers, self.V), dtype=np.int8)
+        state = np.zeros((self.n_walkers, 4), dtype=np.int64)
+        _check(lib().muca_read_state(self._h, _p(spins, ctypes.c_int8), _p(state, ctypes.c_int64)),
+               "muca_read_state")
+        return spins, state
+
+    def write_state(self, spins: np.ndarray, state: np.ndarray):
+        s = np.ascontiguousarray(spins, dtype=np.int8)
+        st = np.ascontiguousarray(state, dtype=np.int64)
+        _check(lib().muca_write_state(self._h, _p(s, ctypes.c_int8), _p(st, ctypes.c_int64)), "muca_write_state")
+
+    def read_accum(self) -> dict:
+        """Per-bin production sums as exact Python integers (same keys as the oracle)."""
+        V1 = self.V + 1
+        sums = np.zeros((5, V1), dtype=np.int64)
+        sm4 = np.zeros((2, V1), dtype=np.uint64)
+        _check(lib().muca_read_accum(self._h, _p(sums, ctypes.c_int64), _p(sm4, ctypes.c_uint64)),
+               "muca_read_accum")
+        return {"H": [int(v) for v in sums[0]], "SJ": [int(v) for v in sums[1]], "SJJ": [int(v) for v in sums[2]],
+                "SA": [int(v) for v in sums[3]], "SM2": [int(v) for v in sums[4]],
+                "SM4": [int(lo) + (int(hi) << 64) for lo, hi in zip(sm4[0], sm4[1])], "V": self.V}
+
+    def reset_accum(self):
+        _check(lib().muca_reset_accum(self._h), "muca_reset_accum")
+
+    def set_launch(self, waves_per_walker: int, blocks_per_lane: int, lds_tables: int = -1):
+        _check(lib().muca_set_launch(self._h, waves_per_walker, blocks_per_lane, lds_tables), "muca_set_launch")
+
+    def get_launch(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().muca_get_launch(self._h, *[ctypes.byref(x) for x in v]), "muca_get_launch")
+        return dict(zip(("waves_per_walker", "blocks_per_lane", "lds_tables", "lds_bytes"), [x.value for x in v]))
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().muca_free(self._h)
+            self._h = None
+            self._tensors = {}
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
