@@ -185,6 +185,16 @@ int muca_set_launch(muca_job *job, int32_t waves_per_walker, int32_t blocks_per_
 int muca_get_launch(const muca_job *job, int32_t *waves_per_walker, int32_t *blocks_per_lane,
                     int32_t *lds_tables, int32_t *lds_bytes);
 
+/* Diagnostics: when enabled, the sweep kernel counts passes (colour-class
+ * groups of sites handled together), rounds of the exact E_Delta resolution,
+ * and accepted moves.  Off by default; a few atomics per pass. */
+int muca_set_stats(muca_job *job, int32_t enable);
+
+/* out[0] = passes, out[1] = fixed-point rounds, out[2] = accepted moves, summed
+ * over walkers since the last reset (3 int64).  reset != 0 zeroes them
+ * afterwards.  Synchronises. */
+int muca_read_stats(muca_job *job, int64_t *out, int32_t reset);
+
 /* Host-only: the threshold tables of the acceptance rule for (L, T, lnW):
  * Bp (25), Rp (V+1) and Rm (V+1) doubles.  Used to check that the tables are
  * bitwise identical to an independent implementation on the same host. */

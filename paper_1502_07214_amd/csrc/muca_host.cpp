@@ -92,7 +92,7 @@ Layout make_layout(const muca_params *p)
     g.hist_bytes = align_up(8 * V1, 256) + 256;  // + error word
     g.off_bp = 0;
     g.off_r = 256;
-    g.off_lnw = g.off_r + align_up(16 * V1, 256);
+    g.off_lnw = g.off_r + align_up(16 * (V1 + 2 * kRPad), 256);
     g.off_nb = g.off_lnw + align_up(8 * V1, 256);
     g.off_site = g.off_nb + align_up((size_t)12 * g.Vp, 256);
     g.tables_bytes = g.off_site + align_up((size_t)2 * g.Vp, 256);
@@ -147,9 +147,37 @@ struct muca_job {
     unsigned char *pin_obs;     // obs buffer
     hipEvent_t ev_tables;
     int64_t recorded;           // sweeps recorded into accum since the last clear
+    int stats;                  // count passes / rounds / accepted moves in the sweep kernel
 };
 
 namespace {
+
+// The passes of one sweep for a launch shape: colour classes in order, each
+// split into groups of 64*wpw*bpl Philox blocks.  Returns the number of passes
+// when a sweep is at most kMaxCachedPasses passes and bpl == 1 (neighbour
+// positions then live in registers), else 0.
+int cached_passes(const Layout &g, int wpw, int bpl, SweepArgs *a)
+{
+    if (bpl != 1) return 0;
+    const int per_pass = 64 * wpw * bpl;
+    int np = 0;
+    unsigned sync = 0u;
+    for (int c = 0; c < g.C; ++c) {
+        const int j0 = g.cls[c] >> 2, j1 = ((g.cls[c + 1] - 1) >> 2) + 1;
+        for (int jb = j0; jb < j1; jb += per_pass) {
+            if (np == kMaxCachedPasses) return 0;
+            if (a) {
+                a->pass_p0[np] = g.cls[c];
+                a->pass_p1[np] = g.cls[c + 1];
+                a->pass_jbase[np] = jb;
+            }
+            ++np;
+        }
+        sync |= 1u << (np - 1);
+    }
+    if (a) a->pass_sync = sync;
+    return np;
+}
 
 struct LaunchPlan {
     bool lds_tables, lds_hist;
@@ -157,7 +185,7 @@ struct LaunchPlan {
     int off_hist, off_lat, off_r, off_nb;
 };
 
-bool plan_launch(const muca_job *j, int wpw, int lds_tables_req, LaunchPlan *out)
+bool plan_launch(const muca_job *j, int wpw, int bpl, int lds_tables_req, LaunchPlan *out)
 {
     const Layout &g = j->g;
     const int wpb = 4 / wpw;
@@ -168,9 +196,9 @@ bool plan_launch(const muca_job *j, int wpw, int lds_tables_req, LaunchPlan *out
         pl->off_lat = (int)off;
         off += align_up((size_t)wpb * g.Vp, 16);
         pl->off_r = (int)off;
-        if (tables) off += align_up(16 * ((size_t)g.V + 1), 16);
+        if (tables) off += align_up(16 * ((size_t)g.V + 1 + 2 * kRPad), 16);
         pl->off_nb = (int)off;
-        if (tables) off += align_up((size_t)12 * g.Vp, 16);
+        if (tables && cached_passes(g, wpw, bpl, nullptr) == 0) off += align_up((size_t)12 * g.Vp, 16);
         pl->lds = off;
         pl->lds_tables = tables;
         pl->lds_hist = hist;
@@ -202,7 +230,7 @@ void default_launch(muca_job *j)
     const int blocks = (largest + 3) / 4 + 1;
     int bpl = blocks > 64 * wpw ? 2 : 1;
     LaunchPlan pl;
-    while (!plan_launch(j, wpw, -1, &pl) && wpw < 4) wpw *= 2;  // fewer walkers per block -> less LDS
+    while (!plan_launch(j, wpw, bpl, -1, &pl) && wpw < 4) wpw *= 2;  // fewer walkers per block -> less LDS
     j->wpw = wpw;
     j->bpl = bpl;
     j->lds_tables_req = -1;
@@ -218,9 +246,10 @@ int upload_tables(muca_job *j)
     std::vector<double> Rp(g.V + 1), Rm(g.V + 1);
     for (int k = 0; k < 32; ++k) Bp[k] = 0.0;
     compute_tables(g.V, j->beta, j->lnW.data(), Bp, Rp.data(), Rm.data());
+    for (int k = 0; k < 2 * (g.V + 1 + 2 * kRPad); ++k) R[k] = 0.0;
     for (int E = 0; E <= g.V; ++E) {
-        R[2 * E] = Rm[E];
-        R[2 * E + 1] = Rp[E];
+        R[2 * (E + kRPad)] = Rm[E];
+        R[2 * (E + kRPad) + 1] = Rp[E];
     }
     std::memcpy(lw, j->lnW.data(), sizeof(double) * (g.V + 1));
     HIP_TRY(hipMemcpyAsync(j->d.tables, j->pin_tables, g.off_nb, hipMemcpyHostToDevice, j->stream));
@@ -363,7 +392,7 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     if (int rc = use_device(j)) return rc;
     const Layout &g = j->g;
     LaunchPlan pl;
-    if (!plan_launch(j, j->wpw, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
+    if (!plan_launch(j, j->wpw, j->bpl, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
     SweepArgs a;
     a.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
     a.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
@@ -373,7 +402,9 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     a.r = reinterpret_cast<const double *>(dt + g.off_r);
     a.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
     a.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
-    a.err = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256));
+    unsigned char *tail = reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256);
+    a.err = reinterpret_cast<int *>(tail);
+    a.stats = j->stats ? reinterpret_cast<unsigned long long *>(tail + 16) : nullptr;
     a.V = g.V;
     a.Vp = g.Vp;
     a.n_walkers = g.n_walkers;
@@ -386,6 +417,7 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     a.lds_off_lat = pl.off_lat;
     a.lds_off_r = pl.off_r;
     a.lds_off_nb = pl.off_nb;
+    a.n_pass = cached_passes(g, j->wpw, j->bpl, &a);
     const bool record = (flags & MUCA_RECORD) != 0;
     int64_t left = n_sweeps;
     while (left > 0) {
@@ -553,13 +585,34 @@ int muca_reset_accum(muca_job *j)
     return clear_accum(j);
 }
 
+int muca_set_stats(muca_job *j, int32_t enable)
+{
+    if (!j) return MUCA_E_INVAL;
+    j->stats = enable ? 1 : 0;
+    return MUCA_OK;
+}
+
+int muca_read_stats(muca_job *j, int64_t *out, int32_t reset)
+{
+    if (!j || !out) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    const size_t off = align_up(8 * ((size_t)j->g.V + 1), 256) + 16;
+    uint64_t v[4];
+    unsigned char *dh = reinterpret_cast<unsigned char *>(j->d.hist) + off;
+    HIP_TRY(hipMemcpyAsync(v, dh, sizeof(v), hipMemcpyDeviceToHost, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    for (int k = 0; k < 3; ++k) out[k] = (int64_t)v[k];
+    if (reset) HIP_TRY(launch_zero(dh, sizeof(v), j->stream));
+    return MUCA_OK;
+}
+
 int muca_set_launch(muca_job *j, int32_t wpw, int32_t bpl, int32_t lds_tables)
 {
     if (!j) return MUCA_E_INVAL;
     if (!(wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2) || lds_tables < -1 || lds_tables > 1)
         return MUCA_E_INVAL;
     LaunchPlan pl;
-    if (!plan_launch(j, wpw, lds_tables, &pl)) return MUCA_E_SIZE;
+    if (!plan_launch(j, wpw, bpl, lds_tables, &pl)) return MUCA_E_SIZE;
     j->wpw = wpw;
     j->bpl = bpl;
     j->lds_tables_req = lds_tables;
@@ -570,7 +623,7 @@ int muca_get_launch(const muca_job *j, int32_t *wpw, int32_t *bpl, int32_t *lds_
 {
     if (!j) return MUCA_E_INVAL;
     LaunchPlan pl;
-    if (!plan_launch(j, j->wpw, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
+    if (!plan_launch(j, j->wpw, j->bpl, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
     if (wpw) *wpw = j->wpw;
     if (bpl) *bpl = j->bpl;
     if (lds_tables) *lds_tables = pl.lds_tables ? 1 : 0;

@@ -12,6 +12,8 @@ constexpr int kBlock = 256;          // threads per block of every kernel: 4 wav
 constexpr int kMaxClasses = 3;       // colours of the visiting order
 constexpr int kLdsFixed = 384;       // B'[32] doubles + scan scratch at the start of LDS
 constexpr int kMaxSweepsPerLaunch = 1 << 26;
+constexpr int kMaxCachedPasses = 4;  // passes per sweep whose neighbour positions stay in registers
+constexpr int kRPad = 4;             // threshold-table entries padded below E = 0 and above E = V
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -31,12 +33,16 @@ struct SweepArgs {
     int32_t *wstate;               // n_walkers x 4: E_J, E_Delta, M, sweeps done
     unsigned long long *hist;      // V+1
     const double *bp;              // 25 (+pad) thresholds 2^31 exp(-beta k)
-    const double *r;               // (V+1) x 2: [E][0] = R_-, [E][1] = R_+
+    const double *r;               // (V+1+2*kRPad) x 2: [E+kRPad][0] = R_-, [E+kRPad][1] = R_+
     const uint16_t *nb;            // 6 x Vp neighbour positions
     unsigned long long *acc;       // 7 x (V+1) production sums
     int *err;                      // device error word (the tail of the hist buffer)
+    unsigned long long *stats;     // null, or [passes, rounds, accepted moves]
     int V, Vp, n_walkers, n_classes;
     int cls[kMaxClasses + 1];
+    int n_pass;                    // > 0: a sweep is exactly these passes (blocks_per_lane 1)
+    int pass_p0[kMaxCachedPasses], pass_p1[kMaxCachedPasses], pass_jbase[kMaxCachedPasses];
+    unsigned pass_sync;            // bit k: synchronise after pass k (end of a colour class)
     uint32_t k0, k1;
     int n_sweeps;
     int lds_hist;                  // 1: histogram in LDS, flushed at the end

@@ -60,197 +60,344 @@ __device__ __forceinline__ int propose(int s, int b)
 }
 
 // ---------------------------------------------------------------------------
+// One pass: the sites of one colour class whose Philox blocks start at jbase,
+// BPL consecutive blocks (4*BPL positions) per lane, GL lanes per walker.
+// ---------------------------------------------------------------------------
+template <int WPW, int BPL>
+struct Walker {
+    static constexpr int GL = 64 * WPW;  // lanes per walker
+    static constexpr int NS = 4 * BPL;   // sites per lane per pass
+    static constexpr int WPB = 4 / WPW;  // walkers per block
+    int8_t *lat;                         // this walker's lattice in LDS
+    const double *R;                     // [E][0] = R_-, [E][1] = R_+
+    const double *sBp;                   // B'[25] in LDS
+    int *sX;                             // [2][4] per-wave exchange words
+    int V, wave, lane, slot, wi, lg;
+    uint32_t w32, k0, k1;
+    int ED;                              // E_Delta of the walker (uniform)
+    unsigned myEJ, myM;                  // this lane's accepted E_J and M changes (mod 2^32)
+    unsigned rounds, accepted;           // diagnostics of the last pass
+
+    // nq[q][dir]: neighbour positions of the 4 sites of block q (two per uint2).
+    __device__ __forceinline__ void pass(int P0, int P1, int jbase, uint32_t sweep, const uint2 (&nq)[BPL][6],
+                                         int *err)
+    {
+        const int j1 = ((P1 - 1) >> 2) + 1;
+        const int j0 = P0 >> 2;
+        const int jb0 = jbase + lg * BPL;
+        // ---- independent part: Philox words, neighbour sums, proposals ----
+        double u[NS], bp[NS];
+        int dd[NS], dej[NS], dsg[NS], snew[NS], sold[NS];
+        bool valid[NS];
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int jb = jb0 + q;
+            const bool blk = jb < j1;
+            const int jbc = blk ? jb : j0;
+            const Ctr4 x = philox10((uint32_t)jbc, w32, sweep, 0u, k0, k1);
+            const int word = *reinterpret_cast<const int *>(lat + 4 * jbc);
+            int h[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int dir = 0; dir < 6; ++dir) {
+                h[0] += lat[nq[q][dir].x & 0xffffu];
+                h[1] += lat[nq[q][dir].x >> 16];
+                h[2] += lat[nq[q][dir].y & 0xffffu];
+                h[3] += lat[nq[q][dir].y >> 16];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * q + t;
+                const int p = 4 * jbc + t;
+                valid[k] = blk && p >= P0 && p < P1;
+                const int s = (int)(int8_t)(word >> (8 * t));
+                const uint32_t xw = x.v[t];
+                const int sn = propose(s, (int)(xw & 1u));
+                u[k] = (double)(xw >> 1);
+                sold[k] = s;
+                snew[k] = sn;
+                dsg[k] = sn - s;
+                dej[k] = -(sn - s) * h[t];
+                dd[k] = sn * sn - s * s;
+                bp[k] = sBp[dej[k] + 12];
+            }
+        }
+        // ---- sequential part: exact fixed point over E_Delta ----
+        // Per site: sens = the decision depends on E_Delta (valid, d != 0),
+        // ridx = 0 for R_-, 1 for R_+.  Branch-free: every site does the same
+        // work, all threshold loads of a round are issued together, and the
+        // loop exit is wave-uniform.  Round 0 decides every site at the
+        // walker's E_Delta; round t decides each site at the E_Delta implied
+        // by the decisions of round t-1 before it (a prefix sum over the
+        // walker's lanes).  Round t reproduces at least the first t sites of
+        // the sequential chain, so the rounds stop at the chain's own result.
+        int sens[NS], ridx[NS], vmask[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            sens[k] = (valid[k] && dd[k] != 0) ? 1 : 0;
+            ridx[k] = dd[k] > 0 ? 1 : 0;
+            vmask[k] = valid[k] ? 1 : 0;
+        }
+        int Eg[NS];
+        int acci[NS];
+        int ex[NS];
+        int total = 0;
+        int changedPrev = 1;  // did the previous round change any guess (round -1: yes)
+        int parity = 0;
+        const int cap = GL * NS + 3;
+        int it = 0;
+        {
+            const double rm = R[2 * ED], rpl = R[2 * ED + 1];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                Eg[k] = ED;
+                const double f = dd[k] == 0 ? 1.0 : (ridx[k] ? rpl : rm);
+                acci[k] = (u[k] < bp[k] * f ? 1 : 0) & vmask[k];
+            }
+        }
+        for (;; ++it) {
+            if (it > 0) {
+                double r[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) r[k] = R[2 * min(max(Eg[k], 0), V) + ridx[k]];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    const double f = dd[k] == 0 ? 1.0 : r[k];
+                    acci[k] = (u[k] < bp[k] * f ? 1 : 0) & vmask[k];
+                }
+            }
+            int run = 0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                ex[k] = run;
+                run += dd[k] & -acci[k];
+            }
+            const unsigned incl = wave_incl_sum((unsigned)run);
+            const int laneOff = (int)incl - run;
+            int waveOff = 0;
+            int wtotal = (int)wave_total(incl);
+            if (WPW > 1) {
+                // one exchange per round: this round's wave total together with
+                // the previous round's "guesses changed" flag
+                if (lane == 63) sX[4 * parity + wave] = (int)((unsigned)wtotal << 1) | changedPrev;
+                __syncthreads();
+                const int4 xw = *reinterpret_cast<const int4 *>(sX + 4 * parity);
+                const int xs[4] = {xw.x, xw.y, xw.z, xw.w};
+                int before = 0, sum = 0, flag = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    flag |= xs[v] & 1;
+                    const int tv = xs[v] >> 1;
+                    const bool mine = (v / WPW) == slot;
+                    before += (mine && (v % WPW) < wi) ? tv : 0;
+                    sum += mine ? tv : 0;
+                }
+                waveOff = before;
+                wtotal = sum;
+                parity ^= 1;
+                // the guesses of this round equal those of the previous one,
+                // which reproduced themselves: this is the fixed point
+                if (__builtin_amdgcn_readfirstlane(flag) == 0) {
+                    total = wtotal;
+                    break;
+                }
+            }
+            int changed = 0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int ne = ED + waveOff + laneOff + ex[k];
+                changed |= (ne != Eg[k] ? 1 : 0) & sens[k];
+                Eg[k] = ne;
+            }
+            changedPrev = __ballot(changed) != 0ull ? 1 : 0;
+            if (WPW == 1 && changedPrev == 0) {
+                total = wtotal;
+                break;
+            }
+            if (it >= cap) {
+                if (lane == 0) atomicOr(err, 1);
+                total = wtotal;
+                break;
+            }
+        }
+        bool acc[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) acc[k] = acci[k] != 0;
+        rounds = (unsigned)(it + 1);
+        // ---- apply the accepted moves ----
+        unsigned nacc = 0;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int jb = jb0 + q;
+            unsigned nw = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * q + t;
+                const int v = acc[k] ? snew[k] : sold[k];
+                nw |= ((unsigned)v & 0xffu) << (8 * t);
+                myEJ += acc[k] ? (unsigned)dej[k] : 0u;
+                myM += acc[k] ? (unsigned)dsg[k] : 0u;
+                nacc += acc[k] ? 1u : 0u;
+            }
+            if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
+        }
+        accepted = nacc;
+        ED += total;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Sweep kernel.
 //   WPW: waves per walker (1, 2, 4); BPL: Philox blocks (4 sites) per lane per
-//   group; RECORD: accumulate production sums; LDS_TABLES: R and neighbour
-//   table staged in LDS.
+//   pass; RECORD: accumulate production sums; LDS_TABLES: R (and, without
+//   register caching, the neighbour table) staged in LDS; NCP > 0: a sweep is
+//   exactly the NCP passes listed in the arguments and each lane keeps the
+//   neighbour positions of its sites in registers for the whole launch.
 // ---------------------------------------------------------------------------
-template <int WPW, int BPL, bool RECORD, bool LDS_TABLES>
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
 __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
 {
-    constexpr int WPB = 4 / WPW;   // walkers per block
-    constexpr int GL = 64 * WPW;   // lanes per walker
-    constexpr int NS = 4 * BPL;    // sites per lane per group
+    constexpr int WPB = 4 / WPW;  // walkers per block
+    using W = Walker<WPW, BPL>;
 
     extern __shared__ __align__(16) unsigned char smem[];
     double *sBp = reinterpret_cast<double *>(smem);
-    int *sTot = reinterpret_cast<int *>(smem + 256);  // [4] wave totals
-    int *sFlag = sTot + 4;                             // [4] wave "changed" flags
-    unsigned *sRed = reinterpret_cast<unsigned *>(sTot + 8);  // [8] per-wave E_J / M sums
+    int *sX = reinterpret_cast<int *>(smem + 256);                   // [8] exchange words
+    unsigned *sRed = reinterpret_cast<unsigned *>(smem + 256 + 80);  // [8] per-wave E_J / M sums
     unsigned *sHist = reinterpret_cast<unsigned *>(smem + a.lds_off_hist);
     int8_t *sLat = reinterpret_cast<int8_t *>(smem + a.lds_off_lat);
 
     const int V = a.V, Vp = a.Vp;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int slot = wave / WPW, wi = wave % WPW;
-    const int lg = wi * 64 + lane;
-    const int walker = blockIdx.x * WPB + slot;
+    W wk;
+    wk.wave = tid >> 6;
+    wk.lane = tid & 63;
+    wk.slot = wk.wave / WPW;
+    wk.wi = wk.wave % WPW;
+    wk.lg = wk.wi * 64 + wk.lane;
+    const int walker = blockIdx.x * WPB + wk.slot;
     const bool live = walker < a.n_walkers;
+    const int lg = wk.lg, lane = wk.lane, wave = wk.wave, slot = wk.slot;
 
     // ---- stage tables and lattices in LDS ----
     for (int k = tid; k < 32; k += kBlock) sBp[k] = (k < 25) ? a.bp[k] : 0.0;
     if (a.lds_hist)
         for (int e = tid; e <= V; e += kBlock) sHist[e] = 0u;
-    const double *R = a.r;
+    const double *R = a.r + 2 * kRPad;  // R[2E + 1] = R_+(E), R[2E] = R_-(E), E in [-kRPad, V + kRPad]
     const uint16_t *NB = a.nb;
     if (LDS_TABLES) {
         double *sR = reinterpret_cast<double *>(smem + a.lds_off_r);
-        uint16_t *sNB = reinterpret_cast<uint16_t *>(smem + a.lds_off_nb);
-        const int nr = 2 * (V + 1);
+        const int nr = 2 * (V + 1 + 2 * kRPad);
         for (int k = tid; k < nr; k += kBlock) sR[k] = a.r[k];
-        const uint4 *gnb = reinterpret_cast<const uint4 *>(a.nb);
-        uint4 *lnb = reinterpret_cast<uint4 *>(sNB);
-        const int nq = (6 * Vp * 2) / 16;
-        for (int k = tid; k < nq; k += kBlock) lnb[k] = gnb[k];
-        R = sR;
-        NB = sNB;
+        R = sR + 2 * kRPad;
+        if (NCP == 0) {
+            uint16_t *sNB = reinterpret_cast<uint16_t *>(smem + a.lds_off_nb);
+            const uint4 *gnb = reinterpret_cast<const uint4 *>(a.nb);
+            uint4 *lnb = reinterpret_cast<uint4 *>(sNB);
+            const int nq = (6 * Vp * 2) / 16;
+            for (int k = tid; k < nq; k += kBlock) lnb[k] = gnb[k];
+            NB = sNB;
+        }
     }
     int8_t *lat = sLat + (size_t)slot * Vp;
     {
         uint4 *dst = reinterpret_cast<uint4 *>(lat);
         const uint4 *src = reinterpret_cast<const uint4 *>(a.lattice + (size_t)(live ? walker : 0) * Vp);
-        for (int k = lg; k < Vp / 16; k += GL) dst[k] = live ? src[k] : make_uint4(0, 0, 0, 0);
+        for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = live ? src[k] : make_uint4(0, 0, 0, 0);
     }
-    int ED = 0, EJ0 = 0, M0 = 0;
+    int EJ0 = 0, M0 = 0;
     uint32_t sweep = 0;
+    wk.ED = 0;
     if (live) {
         const int4 st = reinterpret_cast<const int4 *>(a.wstate)[walker];
-        EJ0 = st.x; ED = st.y; M0 = st.z; sweep = (uint32_t)st.w;
+        EJ0 = st.x;
+        wk.ED = st.y;
+        M0 = st.z;
+        sweep = (uint32_t)st.w;
+    }
+    if (tid < 8) sX[tid] = 0;
+    wk.lat = lat;
+    wk.R = R;
+    wk.sBp = sBp;
+    wk.sX = sX;
+    wk.V = V;
+    wk.w32 = (uint32_t)walker;
+    wk.k0 = a.k0;
+    wk.k1 = a.k1;
+    wk.myEJ = 0u;
+    wk.myM = 0u;
+
+    // neighbour positions of this lane's sites, for the cached passes
+    uint2 nbc[NCP > 0 ? NCP : 1][BPL][6];
+    if (NCP > 0) {
+#pragma unroll
+        for (int cp = 0; cp < (NCP > 0 ? NCP : 1); ++cp) {
+            const int j1 = ((a.pass_p1[cp] - 1) >> 2) + 1;
+#pragma unroll
+            for (int q = 0; q < BPL; ++q) {
+                const int jb = a.pass_jbase[cp] + lg * BPL + q;
+                const int jbc = jb < j1 ? jb : (a.pass_p0[cp] >> 2);
+#pragma unroll
+                for (int dir = 0; dir < 6; ++dir)
+                    nbc[cp][q][dir] = *reinterpret_cast<const uint2 *>(a.nb + dir * Vp + 4 * jbc);
+            }
+        }
     }
     __syncthreads();
 
-    const uint32_t w32 = (uint32_t)walker;
-    unsigned myEJ = 0u, myM = 0u;  // this lane's accepted E_J and M changes (mod 2^32)
-    const int cap = GL * NS + 2;   // the fixed point is reached in <= GL*NS + 1 rounds
+    auto stats_after_pass = [&]() {
+        if (a.stats != nullptr) {
+            const unsigned n = wave_total(wave_incl_sum(wk.accepted));
+            if (live && lane == 0) {
+                atomicAdd(&a.stats[2], (unsigned long long)n);
+                if (lg == 0) {
+                    atomicAdd(&a.stats[0], 1ull);
+                    atomicAdd(&a.stats[1], (unsigned long long)wk.rounds);
+                }
+            }
+        }
+    };
 
     for (int n = 0; n < a.n_sweeps; ++n) {
-        for (int c = 0; c < a.n_classes; ++c) {
-            const int P0 = a.cls[c], P1 = a.cls[c + 1];
-            const int j0 = P0 >> 2, j1 = ((P1 - 1) >> 2) + 1;
-            for (int jbase = j0; jbase < j1; jbase += GL * BPL) {
-                const int jb0 = jbase + lg * BPL;
-                // ---- independent part: Philox, neighbour sums, proposals ----
-                double u[NS], bp[NS];
-                int dd[NS], dej[NS], dsg[NS], snew[NS], sold[NS];
-                bool valid[NS], acc0[NS];
+        if (NCP > 0) {
 #pragma unroll
-                for (int q = 0; q < BPL; ++q) {
-                    const int jb = jb0 + q;
-                    const bool blk = jb < j1;
-                    const int jbc = blk ? jb : j0;
-                    const Ctr4 x = philox10((uint32_t)jbc, w32, sweep, 0u, a.k0, a.k1);
-                    const int word = *reinterpret_cast<const int *>(lat + 4 * jbc);
-                    int h[4] = {0, 0, 0, 0};
-#pragma unroll
-                    for (int dir = 0; dir < 6; ++dir) {
-                        const uint2 nq = *reinterpret_cast<const uint2 *>(NB + dir * Vp + 4 * jbc);
-                        h[0] += lat[nq.x & 0xffffu];
-                        h[1] += lat[nq.x >> 16];
-                        h[2] += lat[nq.y & 0xffffu];
-                        h[3] += lat[nq.y >> 16];
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int k = 4 * q + t;
-                        const int p = 4 * jbc + t;
-                        valid[k] = blk && p >= P0 && p < P1;
-                        const int s = (int)(int8_t)(word >> (8 * t));
-                        const uint32_t xw = x.v[t];
-                        const int sn = propose(s, (int)(xw & 1u));
-                        u[k] = (double)(xw >> 1);
-                        sold[k] = s;
-                        snew[k] = sn;
-                        dsg[k] = sn - s;
-                        dej[k] = -(sn - s) * h[t];
-                        dd[k] = sn * sn - s * s;
-                        bp[k] = sBp[dej[k] + 12];
-                        acc0[k] = u[k] < bp[k];
-                    }
-                }
-                // ---- sequential part: exact fixed point over E_Delta ----
-                int Eg[NS];
-#pragma unroll
-                for (int k = 0; k < NS; ++k) Eg[k] = ED;
-                bool acc[NS];
-                int total = 0;
-                for (int it = 0;; ++it) {
-                    int ex[NS];
-                    int run = 0;
-#pragma unroll
-                    for (int k = 0; k < NS; ++k) {
-                        bool ac = acc0[k];
-                        if (dd[k] != 0) {
-                            const int e = min(max(Eg[k], 0), V);
-                            ac = u[k] < bp[k] * R[2 * e + (dd[k] > 0 ? 1 : 0)];
-                        }
-                        acc[k] = ac && valid[k];
-                        ex[k] = run;
-                        run += acc[k] ? dd[k] : 0;
-                    }
-                    const unsigned incl = wave_incl_sum((unsigned)run);
-                    const int laneOff = (int)incl - run;
-                    int waveOff = 0;
-                    int wtotal = (int)wave_total(incl);
-                    if (WPW > 1) {
-                        if (lane == 63) sTot[wave] = wtotal;
+            for (int cp = 0; cp < (NCP > 0 ? NCP : 1); ++cp) {
+                wk.pass(a.pass_p0[cp], a.pass_p1[cp], a.pass_jbase[cp], sweep, nbc[cp], a.err);
+                stats_after_pass();
+                if ((a.pass_sync >> cp) & 1u) {
+                    if (WPW > 1)
                         __syncthreads();
-                        int sum = 0, before = 0;
-#pragma unroll
-                        for (int v = 0; v < WPW; ++v) {
-                            const int tv = sTot[slot * WPW + v];
-                            before += (v < wi) ? tv : 0;
-                            sum += tv;
-                        }
-                        waveOff = before;
-                        wtotal = sum;
-                    }
-                    bool changed = false;
-#pragma unroll
-                    for (int k = 0; k < NS; ++k) {
-                        const int ne = ED + waveOff + laneOff + ex[k];
-                        changed |= valid[k] && dd[k] != 0 && ne != Eg[k];
-                        Eg[k] = ne;
-                    }
-                    bool any = __ballot(changed) != 0ull;
-                    if (WPW > 1) {
-                        if (lane == 0) sFlag[wave] = any ? 1 : 0;
-                        __syncthreads();
-                        any = (sFlag[0] | sFlag[1] | sFlag[2] | sFlag[3]) != 0;
-                    }
-                    if (!any || it >= cap) {
-                        if (any && lane == 0) atomicOr(a.err, 1);
-                        total = wtotal;
-                        break;
-                    }
+                    else
+                        wave_sync_lds();
                 }
-                // ---- apply the accepted moves ----
-#pragma unroll
-                for (int q = 0; q < BPL; ++q) {
-                    const int jb = jb0 + q;
-                    unsigned nw = 0;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int k = 4 * q + t;
-                        const int v = acc[k] ? snew[k] : sold[k];
-                        nw |= ((unsigned)v & 0xffu) << (8 * t);
-                        myEJ += acc[k] ? (unsigned)dej[k] : 0u;
-                        myM += acc[k] ? (unsigned)dsg[k] : 0u;
-                    }
-                    if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
-                }
-                ED += total;
             }
-            if (WPW > 1)
-                __syncthreads();
-            else
-                wave_sync_lds();
+        } else {
+            for (int c = 0; c < a.n_classes; ++c) {
+                const int P0 = a.cls[c], P1 = a.cls[c + 1];
+                const int j0 = P0 >> 2, j1 = ((P1 - 1) >> 2) + 1;
+                for (int jbase = j0; jbase < j1; jbase += W::GL * BPL) {
+                    uint2 nq[BPL][6];
+#pragma unroll
+                    for (int q = 0; q < BPL; ++q) {
+                        const int jb = jbase + lg * BPL + q;
+                        const int jbc = jb < j1 ? jb : j0;
+#pragma unroll
+                        for (int dir = 0; dir < 6; ++dir)
+                            nq[q][dir] = *reinterpret_cast<const uint2 *>(NB + dir * Vp + 4 * jbc);
+                    }
+                    wk.pass(P0, P1, jbase, sweep, nq, a.err);
+                    stats_after_pass();
+                }
+                if (WPW > 1)
+                    __syncthreads();
+                else
+                    wave_sync_lds();
+            }
         }
         sweep += 1u;
         // ---- measurement after the sweep ----
         if (RECORD) {
-            unsigned ej = wave_total(wave_incl_sum(myEJ));
-            unsigned m = wave_total(wave_incl_sum(myM));
+            unsigned ej = wave_total(wave_incl_sum(wk.myEJ));
+            unsigned m = wave_total(wave_incl_sum(wk.myM));
             if (WPW > 1) {
                 if (lane == 0) {
                     sRed[2 * wave] = ej;
@@ -266,6 +413,7 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
                 }
             }
             if (live && lg == 0) {
+                const int ED = wk.ED;
                 const long long EJ = (long long)(int)((unsigned)EJ0 + ej);
                 const long long M = (long long)(int)((unsigned)M0 + m);
                 const int V1 = V + 1;
@@ -283,15 +431,15 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
         }
         if (live && lg == 0) {
             if (a.lds_hist)
-                atomicAdd(&sHist[ED], 1u);
+                atomicAdd(&sHist[wk.ED], 1u);
             else
-                atomicAdd(&a.hist[ED], 1ull);
+                atomicAdd(&a.hist[wk.ED], 1ull);
         }
     }
 
     // ---- write back ----
-    unsigned ej = wave_total(wave_incl_sum(myEJ));
-    unsigned m = wave_total(wave_incl_sum(myM));
+    unsigned ej = wave_total(wave_incl_sum(wk.myEJ));
+    unsigned m = wave_total(wave_incl_sum(wk.myM));
     __syncthreads();  // every wave is done with sRed and sHist of the last sweep
     if (lane == 0) {
         sRed[2 * wave] = ej;
@@ -308,10 +456,10 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
     if (live) {
         uint4 *dst = reinterpret_cast<uint4 *>(a.lattice + (size_t)walker * Vp);
         const uint4 *src = reinterpret_cast<const uint4 *>(lat);
-        for (int k = lg; k < Vp / 16; k += GL) dst[k] = src[k];
+        for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = src[k];
         if (lg == 0)
             reinterpret_cast<int4 *>(a.wstate)[walker] =
-                make_int4((int)((unsigned)EJ0 + ej), ED, (int)((unsigned)M0 + m), (int)sweep);
+                make_int4((int)((unsigned)EJ0 + ej), wk.ED, (int)((unsigned)M0 + m), (int)sweep);
     }
     if (a.lds_hist)
         for (int e = tid; e <= V; e += kBlock) {
@@ -534,10 +682,10 @@ hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int WPW, int BPL, bool RECORD, bool LDS_TABLES>
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
 static hipError_t launch_sweep_t(const SweepArgs &a, size_t lds, hipStream_t s)
 {
-    auto kern = muca_sweep_kernel<WPW, BPL, RECORD, LDS_TABLES>;
+    auto kern = muca_sweep_kernel<WPW, BPL, RECORD, LDS_TABLES, NCP>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -547,14 +695,28 @@ static hipError_t launch_sweep_t(const SweepArgs &a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES>
+static hipError_t launch_sweep_n(const SweepArgs &a, size_t lds, hipStream_t s)
+{
+    if constexpr (BPL == 1) {
+        switch (a.n_pass) {
+        case 2: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 2>(a, lds, s);
+        case 3: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 3>(a, lds, s);
+        case 4: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 4>(a, lds, s);
+        default: break;
+        }
+    }
+    return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 0>(a, lds, s);
+}
+
 template <int WPW, int BPL>
 static hipError_t launch_sweep_b(const SweepArgs &a, bool record, bool lds_tables, size_t lds, hipStream_t s)
 {
     if (record)
-        return lds_tables ? launch_sweep_t<WPW, BPL, true, true>(a, lds, s)
-                          : launch_sweep_t<WPW, BPL, true, false>(a, lds, s);
-    return lds_tables ? launch_sweep_t<WPW, BPL, false, true>(a, lds, s)
-                      : launch_sweep_t<WPW, BPL, false, false>(a, lds, s);
+        return lds_tables ? launch_sweep_n<WPW, BPL, true, true>(a, lds, s)
+                          : launch_sweep_n<WPW, BPL, true, false>(a, lds, s);
+    return lds_tables ? launch_sweep_n<WPW, BPL, false, true>(a, lds, s)
+                      : launch_sweep_n<WPW, BPL, false, false>(a, lds, s);
 }
 
 hipError_t launch_sweep(const SweepArgs &a, int wpw, int bpl, bool record, bool lds_tables, size_t lds,

@@ -27,7 +27,7 @@ OBS_FIELDS = (
 EXPORTS = (
     "muca_query_sizes", "muca_init", "muca_sweep", "muca_reduce_hist", "muca_update_weights",
     "muca_set_weights", "muca_get_weights", "muca_reweight", "muca_read_state", "muca_write_state",
-    "muca_read_accum", "muca_reset_accum", "muca_set_launch", "muca_get_launch", "muca_host_tables",
+    "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free",
 )
 
@@ -74,6 +74,8 @@ def lib():
     L.muca_write_state.argtypes = [vp, P(ctypes.c_int8), P(i64)]
     L.muca_read_accum.argtypes = [vp, P(i64), P(ctypes.c_uint64)]
     L.muca_reset_accum.argtypes = [vp]
+    L.muca_set_stats.argtypes = [vp, i32]
+    L.muca_read_stats.argtypes = [vp, P(i64), i32]
     L.muca_set_launch.argtypes = [vp, i32, i32, i32]
     L.muca_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     L.muca_host_tables.argtypes = [i32, dbl, P(dbl), P(dbl), P(dbl), P(dbl)]
@@ -225,6 +227,14 @@ class MucaJob:
 
     def reset_accum(self):
         _check(lib().muca_reset_accum(self._h), "muca_reset_accum")
+
+    def set_stats(self, enable: bool = True):
+        _check(lib().muca_set_stats(self._h, 1 if enable else 0), "muca_set_stats")
+
+    def read_stats(self, reset: bool = False) -> dict:
+        v = np.zeros(3, dtype=np.int64)
+        _check(lib().muca_read_stats(self._h, _p(v, ctypes.c_int64), 1 if reset else 0), "muca_read_stats")
+        return {"passes": int(v[0]), "rounds": int(v[1]), "accepted": int(v[2])}
 
     def set_launch(self, waves_per_walker: int, blocks_per_lane: int, lds_tables: int = -1):
         _check(lib().muca_set_launch(self._h, waves_per_walker, blocks_per_lane, lds_tables), "muca_set_launch")
