@@ -195,6 +195,41 @@ int muca_set_stats(muca_job *job, int32_t enable);
  * afterwards.  Synchronises. */
 int muca_read_stats(muca_job *job, int64_t *out, int32_t reset);
 
+/* ---------------------------------------------------------------------------
+ * Batched persistent launch: the walkers of several jobs (different L, T and
+ * weights) swept by one kernel launch.  Blocks pull work tiles (walkers of one
+ * job) from a device work counter, heaviest jobs first, so jobs of uneven size
+ * share the device.  Every walker runs exactly the chain it runs under
+ * muca_sweep on its own job: results do not depend on the batching.
+ * ------------------------------------------------------------------------- */
+typedef struct muca_batch muca_batch;
+
+/* Device bytes the batch needs for its job table and work list (for jobs[0..n)). */
+int muca_batch_query_size(muca_job *const *jobs, int32_t n_jobs, size_t *bytes);
+
+/* Create a batch over n_jobs (>= 1) distinct jobs created on the same device
+ * with the same stream.  dev_buffer: caller-owned device memory of at least
+ * muca_batch_query_size bytes, 256-aligned, valid until muca_batch_free.  The
+ * jobs stay owned by the caller and must outlive the batch.  Synchronises. */
+int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, size_t bytes,
+                      muca_batch **out);
+
+/* Launch shape of the batched kernel (results do not depend on it):
+ * waves_per_walker in {1, 2, 4}, blocks_per_lane in {1, 2}; blocks <= 0 fills
+ * the device (occupancy query).  MUCA_E_SIZE if the lattice slots of the
+ * largest job do not fit in LDS. */
+int muca_batch_set_launch(muca_batch *batch, int32_t waves_per_walker, int32_t blocks_per_lane,
+                          int32_t blocks);
+
+/* n_sweeps (0..MUCA_MAX_SWEEPS_PER_CALL) sweeps of every walker of every job in
+ * the batch, in one persistent launch per at most 2^26 sweeps; flags as for
+ * muca_sweep.  Each job's histogram (and production sums with MUCA_RECORD) is
+ * added to as by muca_sweep.  Asynchronous on the jobs' stream. */
+int muca_batch_sweep(muca_batch *batch, int64_t n_sweeps, uint32_t flags);
+
+/* Release the batch's host resources (waits for queued work).  NULL ignored. */
+void muca_batch_free(muca_batch *batch);
+
 /* Host-only: the threshold tables of the acceptance rule for (L, T, lnW):
  * Bp (25), Rp (V+1) and Rm (V+1) doubles.  Used to check that the tables are
  * bitwise identical to an independent implementation on the same host. */

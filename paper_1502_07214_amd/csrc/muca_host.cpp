@@ -648,6 +648,189 @@ int muca_host_order(int32_t L, int32_t *order)
     return MUCA_OK;
 }
 
+}  // extern "C"
+
+struct muca_batch {
+    std::vector<muca_job *> jobs;
+    hipStream_t stream;
+    int device;
+    unsigned char *dev;
+    size_t bytes;
+    int n_tiles;
+    int wpw, bpl, blocks;
+    int max_vp;
+    size_t total_walkers;
+};
+
+namespace {
+
+size_t batch_bytes(size_t n_jobs, size_t walkers)
+{
+    return align_up(n_jobs * sizeof(BatchJob), 256) + align_up(walkers * sizeof(int2), 256) + 256;
+}
+
+// Tiles of 4/wpw consecutive walkers of one job, jobs with the most work per
+// walker (largest V) first.
+int build_tiles(muca_batch *b, int wpw, std::vector<int2> &tiles)
+{
+    const int wpb = 4 / wpw;
+    std::vector<int> idx(b->jobs.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return b->jobs[x]->g.V > b->jobs[y]->g.V; });
+    tiles.clear();
+    for (int jx : idx)
+        for (int w = 0; w < b->jobs[jx]->g.n_walkers; w += wpb) tiles.push_back(make_int2(jx, w));
+    return (int)tiles.size();
+}
+
+int upload_batch(muca_batch *b)
+{
+    std::vector<int2> tiles;
+    b->n_tiles = build_tiles(b, b->wpw, tiles);
+    std::vector<BatchJob> bj(b->jobs.size());
+    for (size_t k = 0; k < b->jobs.size(); ++k) {
+        const muca_job *j = b->jobs[k];
+        const Layout &g = j->g;
+        unsigned char *dt = reinterpret_cast<unsigned char *>(j->d.tables);
+        BatchJob &J = bj[k];
+        J.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
+        J.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
+        J.hist = reinterpret_cast<unsigned long long *>(j->d.hist);
+        J.bp = reinterpret_cast<const double *>(dt + g.off_bp);
+        J.r = reinterpret_cast<const double *>(dt + g.off_r);
+        J.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
+        J.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
+        J.err = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256));
+        J.V = g.V;
+        J.Vp = g.Vp;
+        J.n_walkers = g.n_walkers;
+        J.n_classes = g.C;
+        for (int c = 0; c <= kMaxClasses; ++c) J.cls[c] = g.cls[c];
+        J.k0 = j->k0;
+        J.k1 = j->k1;
+    }
+    const size_t off_tiles = align_up(bj.size() * sizeof(BatchJob), 256);
+    HIP_TRY(hipMemcpyAsync(b->dev, bj.data(), bj.size() * sizeof(BatchJob), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->dev + off_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return MUCA_OK;
+}
+
+size_t batch_lds(const muca_batch *b, int wpw) { return kLdsFixed + align_up((size_t)(4 / wpw) * b->max_vp, 16); }
+
+}  // namespace
+
+extern "C" {
+
+int muca_batch_query_size(muca_job *const *jobs, int32_t n_jobs, size_t *bytes)
+{
+    if (!jobs || n_jobs < 1 || !bytes) return MUCA_E_INVAL;
+    size_t walkers = 0;
+    for (int k = 0; k < n_jobs; ++k) {
+        if (!jobs[k]) return MUCA_E_INVAL;
+        walkers += (size_t)jobs[k]->g.n_walkers;
+    }
+    *bytes = batch_bytes((size_t)n_jobs, walkers);
+    return MUCA_OK;
+}
+
+int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, size_t bytes, muca_batch **out)
+{
+    if (!out) return MUCA_E_INVAL;
+    *out = nullptr;
+    size_t need = 0;
+    if (int rc = muca_batch_query_size(jobs, n_jobs, &need)) return rc;
+    if (!dev_buffer || (reinterpret_cast<uintptr_t>(dev_buffer) & 255u)) return MUCA_E_INVAL;
+    if (bytes < need) return MUCA_E_SIZE;
+    for (int k = 0; k < n_jobs; ++k) {
+        if (jobs[k]->stream != jobs[0]->stream || jobs[k]->device != jobs[0]->device) return MUCA_E_INVAL;
+        for (int m = 0; m < k; ++m)
+            if (jobs[m] == jobs[k]) return MUCA_E_INVAL;
+    }
+    muca_batch *b = new (std::nothrow) muca_batch();
+    if (!b) return MUCA_E_SIZE;
+    b->jobs.assign(jobs, jobs + n_jobs);
+    b->stream = jobs[0]->stream;
+    b->device = jobs[0]->device;
+    b->dev = reinterpret_cast<unsigned char *>(dev_buffer);
+    b->bytes = bytes;
+    b->max_vp = 0;
+    b->total_walkers = 0;
+    for (muca_job *j : b->jobs) {
+        b->max_vp = std::max(b->max_vp, j->g.Vp);
+        b->total_walkers += (size_t)j->g.n_walkers;
+    }
+    b->wpw = 1;
+    b->bpl = 1;
+    b->blocks = 0;
+    const int max_lds = jobs[0]->max_lds;
+    while (batch_lds(b, b->wpw) > (size_t)max_lds && b->wpw < 4) b->wpw *= 2;
+    if (batch_lds(b, b->wpw) > (size_t)max_lds) {
+        delete b;
+        return MUCA_E_SIZE;
+    }
+    if (int rc = use_device(jobs[0])) {
+        delete b;
+        return rc;
+    }
+    if (int rc = upload_batch(b)) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return MUCA_OK;
+}
+
+int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t blocks)
+{
+    if (!b || !(wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2)) return MUCA_E_INVAL;
+    if (batch_lds(b, wpw) > (size_t)b->jobs[0]->max_lds) return MUCA_E_SIZE;
+    if (int rc = use_device(b->jobs[0])) return rc;
+    const int old = b->wpw;
+    b->wpw = wpw;
+    b->bpl = bpl;
+    b->blocks = blocks > 0 ? blocks : 0;
+    if (old != wpw) return upload_batch(b);
+    return MUCA_OK;
+}
+
+int muca_batch_sweep(muca_batch *b, int64_t n_sweeps, uint32_t flags)
+{
+    if (!b || n_sweeps < 0 || (flags & ~MUCA_RECORD)) return MUCA_E_INVAL;
+    if (n_sweeps > MUCA_MAX_SWEEPS_PER_CALL) return MUCA_E_OVERFLOW;
+    if (n_sweeps == 0) return MUCA_OK;
+    if (int rc = use_device(b->jobs[0])) return rc;
+    const size_t off_tiles = align_up(b->jobs.size() * sizeof(BatchJob), 256);
+    const size_t off_counter = off_tiles + align_up(b->total_walkers * sizeof(int2), 256);
+    BatchArgs a;
+    a.jobs = reinterpret_cast<const BatchJob *>(b->dev);
+    a.tiles = reinterpret_cast<const int2 *>(b->dev + off_tiles);
+    a.n_tiles = b->n_tiles;
+    a.counter = reinterpret_cast<unsigned *>(b->dev + off_counter);
+    a.lds_off_lat = kLdsFixed;
+    const bool record = (flags & MUCA_RECORD) != 0;
+    int64_t left = n_sweeps;
+    while (left > 0) {
+        const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
+        a.n_sweeps = chunk;
+        HIP_TRY(launch_zero(b->dev + off_counter, 16, b->stream));
+        HIP_TRY(launch_batch(a, b->wpw, b->bpl, record, batch_lds(b, b->wpw), b->blocks, b->stream));
+        left -= chunk;
+    }
+    if (record)
+        for (muca_job *j : b->jobs) j->recorded += n_sweeps;
+    return MUCA_OK;
+}
+
+void muca_batch_free(muca_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
 const char *muca_strerror(int code)
 {
     switch (code) {

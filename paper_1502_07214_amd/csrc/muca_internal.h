@@ -67,11 +67,37 @@ struct ReweightArgs {
     double beta;
 };
 
+// One job of a batched launch (device-resident table).
+struct BatchJob {
+    int8_t *lattice;
+    int32_t *wstate;
+    unsigned long long *hist;
+    const double *bp;
+    const double *r;
+    const uint16_t *nb;
+    unsigned long long *acc;
+    int *err;
+    int V, Vp, n_walkers, n_classes;
+    int cls[kMaxClasses + 1];
+    uint32_t k0, k1;
+};
+
+struct BatchArgs {
+    const BatchJob *jobs;
+    const int2 *tiles;       // (job, first walker), heaviest first
+    int n_tiles;
+    unsigned *counter;       // work counter, zero at launch
+    int n_sweeps;
+    int lds_off_lat;         // LDS offset of the lattice slots (sized for the largest job)
+};
+
 // Launchers (muca_kernels.hip).  Return the hipError_t of the launch.
 hipError_t launch_init(const InitArgs &a, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs &a, int waves_per_walker, int blocks_per_lane, bool record,
                         bool lds_tables, size_t lds_bytes, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s);
+// blocks <= 0: as many blocks as fit on the device at once
+hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, size_t lds, int blocks, hipStream_t s);
 
 }  // namespace muca

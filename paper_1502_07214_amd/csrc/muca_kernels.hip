@@ -254,12 +254,10 @@ struct Walker {
 //   neighbour positions of its sites in registers for the whole launch.
 // ---------------------------------------------------------------------------
 template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
-__global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, unsigned char *smem)
 {
-    constexpr int WPB = 4 / WPW;  // walkers per block
     using W = Walker<WPW, BPL>;
 
-    extern __shared__ __align__(16) unsigned char smem[];
     double *sBp = reinterpret_cast<double *>(smem);
     int *sX = reinterpret_cast<int *>(smem + 256);                   // [8] exchange words
     unsigned *sRed = reinterpret_cast<unsigned *>(smem + 256 + 80);  // [8] per-wave E_J / M sums
@@ -274,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
     wk.slot = wk.wave / WPW;
     wk.wi = wk.wave % WPW;
     wk.lg = wk.wi * 64 + wk.lane;
-    const int walker = blockIdx.x * WPB + wk.slot;
+    const int walker = walker_base + wk.slot;
     const bool live = walker < a.n_walkers;
     const int lg = wk.lg, lane = wk.lane, wave = wk.wave, slot = wk.slot;
 
@@ -466,6 +464,64 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
             const unsigned cnt = sHist[e];
             if (cnt) atomicAdd(&a.hist[e], (unsigned long long)cnt);
         }
+}
+
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
+__global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_tile<WPW, BPL, RECORD, LDS_TABLES, NCP>(a, (int)blockIdx.x * (4 / WPW), smem);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent sweep: walkers of many jobs (different L, T, weights) in
+// one launch.  Blocks pull tiles (4 / WPW walkers of one job) from a work
+// counter until the list is exhausted; the host orders the list heaviest
+// first.  Thresholds and neighbour tables are read through the caches, spins
+// are staged in LDS, histograms go straight to each job's buffer.  Each walker
+// runs exactly the chain it runs in its own job's launch.
+// ---------------------------------------------------------------------------
+template <int WPW, int BPL, bool RECORD>
+__global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sTile;
+    for (;;) {
+        if (threadIdx.x == 0) sTile = (int)atomicAdd(b.counter, 1u);
+        __syncthreads();
+        const int t = sTile;
+        __syncthreads();
+        if (t >= b.n_tiles) break;
+        const int2 tile = b.tiles[t];
+        const BatchJob &J = b.jobs[tile.x];
+        SweepArgs a;
+        a.lattice = J.lattice;
+        a.wstate = J.wstate;
+        a.hist = J.hist;
+        a.bp = J.bp;
+        a.r = J.r;
+        a.nb = J.nb;
+        a.acc = J.acc;
+        a.err = J.err;
+        a.stats = nullptr;
+        a.V = J.V;
+        a.Vp = J.Vp;
+        a.n_walkers = J.n_walkers;
+        a.n_classes = J.n_classes;
+#pragma unroll
+        for (int c = 0; c <= kMaxClasses; ++c) a.cls[c] = J.cls[c];
+        a.n_pass = 0;
+        a.pass_sync = 0u;
+        a.k0 = J.k0;
+        a.k1 = J.k1;
+        a.n_sweeps = b.n_sweeps;
+        a.lds_hist = 0;
+        a.lds_off_hist = kLdsFixed;
+        a.lds_off_lat = b.lds_off_lat;
+        a.lds_off_r = 0;
+        a.lds_off_nb = 0;
+        sweep_tile<WPW, BPL, RECORD, false, 0>(a, tile.y, smem);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -717,6 +773,40 @@ static hipError_t launch_sweep_b(const SweepArgs &a, bool record, bool lds_table
                           : launch_sweep_n<WPW, BPL, true, false>(a, lds, s);
     return lds_tables ? launch_sweep_n<WPW, BPL, false, true>(a, lds, s)
                       : launch_sweep_n<WPW, BPL, false, false>(a, lds, s);
+}
+
+template <int WPW, int BPL, bool RECORD>
+static hipError_t launch_batch_t(const BatchArgs &b, size_t lds, int blocks, hipStream_t s)
+{
+    auto kern = muca_batch_kernel<WPW, BPL, RECORD>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (blocks <= 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), kBlock, lds);
+        if (e != hipSuccess) return e;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        blocks = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 256);
+        if (blocks > b.n_tiles) blocks = b.n_tiles;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), lds, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, size_t lds, int blocks, hipStream_t s)
+{
+    if (wpw == 1) {
+        if (bpl == 1) return record ? launch_batch_t<1, 1, true>(b, lds, blocks, s) : launch_batch_t<1, 1, false>(b, lds, blocks, s);
+        return record ? launch_batch_t<1, 2, true>(b, lds, blocks, s) : launch_batch_t<1, 2, false>(b, lds, blocks, s);
+    }
+    if (wpw == 2) {
+        if (bpl == 1) return record ? launch_batch_t<2, 1, true>(b, lds, blocks, s) : launch_batch_t<2, 1, false>(b, lds, blocks, s);
+        return record ? launch_batch_t<2, 2, true>(b, lds, blocks, s) : launch_batch_t<2, 2, false>(b, lds, blocks, s);
+    }
+    if (bpl == 1) return record ? launch_batch_t<4, 1, true>(b, lds, blocks, s) : launch_batch_t<4, 1, false>(b, lds, blocks, s);
+    return record ? launch_batch_t<4, 2, true>(b, lds, blocks, s) : launch_batch_t<4, 2, false>(b, lds, blocks, s);
 }
 
 hipError_t launch_sweep(const SweepArgs &a, int wpw, int bpl, bool record, bool lds_tables, size_t lds,

@@ -28,7 +28,8 @@ EXPORTS = (
     "muca_query_sizes", "muca_init", "muca_sweep", "muca_reduce_hist", "muca_update_weights",
     "muca_set_weights", "muca_get_weights", "muca_reweight", "muca_read_state", "muca_write_state",
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
-    "muca_host_order", "muca_strerror", "muca_free",
+    "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
+    "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free",
 )
 
 
@@ -84,8 +85,14 @@ def lib():
     L.muca_strerror.restype = ctypes.c_char_p
     L.muca_free.argtypes = [vp]
     L.muca_free.restype = None
+    L.muca_batch_query_size.argtypes = [P(vp), i32, sz]
+    L.muca_batch_create.argtypes = [P(vp), i32, vp, ctypes.c_size_t, P(vp)]
+    L.muca_batch_set_launch.argtypes = [vp, i32, i32, i32]
+    L.muca_batch_sweep.argtypes = [vp, i64, u32]
+    L.muca_batch_free.argtypes = [vp]
+    L.muca_batch_free.restype = None
     for name in EXPORTS:
-        if name not in ("muca_strerror", "muca_free"):
+        if name not in ("muca_strerror", "muca_free", "muca_batch_free"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -249,6 +256,44 @@ class MucaJob:
             lib().muca_free(self._h)
             self._h = None
             self._tensors = {}
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class MucaBatch:
+    """Several MucaJobs (same device and stream) swept by one persistent launch."""
+
+    def __init__(self, jobs: Sequence[MucaJob]):
+        import torch
+
+        self.jobs = list(jobs)
+        arr = (ctypes.c_void_p * len(self.jobs))(*[j._h.value for j in self.jobs])
+        nbytes = ctypes.c_size_t()
+        _check(lib().muca_batch_query_size(arr, len(self.jobs), ctypes.byref(nbytes)), "muca_batch_query_size")
+        dev = self.jobs[0].device
+        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        ptr = self._buf.data_ptr() + (-self._buf.data_ptr()) % 256
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib().muca_batch_create(arr, len(self.jobs), ctypes.c_void_p(ptr), nbytes.value, ctypes.byref(h)),
+                   "muca_batch_create")
+        self._h = h
+
+    def set_launch(self, waves_per_walker: int, blocks_per_lane: int, blocks: int = 0):
+        _check(lib().muca_batch_set_launch(self._h, waves_per_walker, blocks_per_lane, blocks), "muca_batch_set_launch")
+
+    def sweep(self, n_sweeps: int, record: bool = False):
+        _check(lib().muca_batch_sweep(self._h, int(n_sweeps), MUCA_RECORD if record else 0), "muca_batch_sweep")
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().muca_batch_free(self._h)
+            self._h = None
+            self._buf = None
 
     def __del__(self):
         try:
