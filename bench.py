@@ -36,6 +36,11 @@ WORKLOAD = "l12_t2_w256"
 ALGO_SLOTS_PER_ATTEMPT = 75
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate VALU lane slots.
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# HBM bytes per 10^4-sweep launch of muca_sweep_kernel<4,1,false,true,2> on this
+# workload: FETCH_SIZE + WRITE_SIZE from rocprofv3, each scaled by the same
+# counter's reading on a plain 1 GiB copy (profiles/sweep_kernel_l12_t2_w256_pmc.txt).
+TRAFFIC_KERNEL = "muca_sweep_kernel<4, 1, false, true, 2>"
+TRAFFIC_BYTES_PER_LAUNCH = 1834702
 
 
 def parse():
@@ -45,6 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, served and saturation legs")
     ap.add_argument("--launch", default=None, help="wpw,bpl,lds_tables (default: library's choice)")
     return ap.parse_args()
 
@@ -75,6 +81,83 @@ def run_step(w, deltas, events=None, launch=None):
     shape = job.get_launch()
     job.free()
     return flat, obs, shape
+
+
+def batched_leg(launch_shape=None):
+    """Mixed (L, T) jobs: one persistent launch per iteration vs one launch per job."""
+    import torch
+
+    from paper_1502_07214_amd import MucaBatch, MucaJob, workloads
+
+    specs = workloads.batched_jobs()
+    it, sw = workloads.BATCHED["iterations"], workloads.BATCHED["sweeps"]
+    per_sweep = sum(n * L ** 3 for (L, T, n, s) in specs)
+    out = {"jobs": len(specs), "walkers": sum(n for (_, _, n, _) in specs), "iterations": it, "sweeps": sw,
+           "attempts": per_sweep * it * sw}
+    for mode in ("batched", "plain"):
+        jobs = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
+        batch = MucaBatch(jobs) if mode == "batched" else None
+        if batch is not None and launch_shape:
+            batch.set_launch(*launch_shape)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(it):
+            if batch is not None:
+                batch.sweep(sw)
+            else:
+                for j in jobs:
+                    j.sweep(sw)
+            for j in jobs:
+                j.update_weights(j.reduce_hist())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[mode + "_attempts_per_s"] = out["attempts"] / dt
+        out[mode + "_s"] = dt
+        if batch is not None:
+            batch.free()
+        for j in jobs:
+            j.free()
+    out["speedup"] = out["batched_attempts_per_s"] / out["plain_attempts_per_s"]
+    return out
+
+
+def served_leg():
+    """Poisson stream of MUCA jobs: continuous batching vs one job at a time."""
+    from paper_1502_07214_amd import workloads
+    from paper_1502_07214_amd.serve import ServeConfig, poisson_requests, serve, serve_plain
+
+    sp = workloads.SERVED
+    reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"])
+    cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"])
+    out = {"spec": {k: v for k, v in sp.items()}}
+    for mode, fn in (("served", serve), ("plain", serve_plain)):
+        r = fn(reqs, cfg)
+        out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "makespan_s", "jobs_per_s", "attempts_per_s",
+                                       "latency_p50_s", "latency_p99_s", "iterations_p50", "queue_depth_max")}
+    return out
+
+
+def saturation_leg(launch_ms_out=None):
+    import torch
+
+    from paper_1502_07214_amd import MucaJob, workloads
+
+    s = workloads.SATURATION
+    job = MucaJob(s["L"], s["T"], s["n_walkers"], seed=s["seed"], max_delta=1)
+    job.sweep(10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    job.sweep(s["sweeps"])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rate = s["n_walkers"] * s["L"] ** 3 * s["sweeps"] / (ms * 1e-3)
+    shape = job.get_launch()
+    job.free()
+    return {"workload": f"L={s['L']} T={s['T']} walkers={s['n_walkers']} sweeps={s['sweeps']}", "launch": shape,
+            "kernel_attempts_per_s": rate, "launch_ms": ms,
+            "roofline_frac": rate * ALGO_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S}
 
 
 def cpu_baseline(w, deltas):
@@ -156,9 +239,18 @@ def main():
         "sweep_launch_ms": launch_ms,
         "final_flatness": flat,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
+                     "traffic": TRAFFIC_BYTES_PER_LAUNCH if shape == {"waves_per_walker": 4, "blocks_per_lane": 1,
+                                                                      "lds_tables": 1, "lds_bytes": 36832} else None,
                      "kernel": "muca_sweep_kernel", "slots_per_attempt": ALGO_SLOTS_PER_ATTEMPT},
     }
+    if not args.no_extra:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg()
+        print("[bench] saturation leg", file=sys.stderr, flush=True)
+        out["saturation"] = saturation_leg()
+        print("[bench] served leg", file=sys.stderr, flush=True)
+        out["served"] = served_leg()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, deltas)

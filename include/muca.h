@@ -230,6 +230,11 @@ int muca_batch_sweep(muca_batch *batch, int64_t n_sweeps, uint32_t flags);
 /* Release the batch's host resources (waits for queued work).  NULL ignored. */
 void muca_batch_free(muca_batch *batch);
 
+/* Host-only: flatness min / mean of hist[lo..hi] (inclusive bins, 0 <= lo <= hi),
+ * the convergence measure of the weight iteration restricted to a window of
+ * E_Delta; 0 when the window holds no entries. */
+int muca_flatness(const int64_t *hist, int32_t lo, int32_t hi, double *flatness_out);
+
 /* Host-only: the threshold tables of the acceptance rule for (L, T, lnW):
  * Bp (25), Rp (V+1) and Rm (V+1) doubles.  Used to check that the tables are
  * bitwise identical to an independent implementation on the same host. */

@@ -216,24 +216,25 @@ bool plan_launch(const muca_job *j, int wpw, int bpl, int lds_tables_req, Launch
 
 void default_launch(muca_job *j)
 {
+    // Measured on MI355X (see the design notes): few walkers -> spread each
+    // walker over a whole block (4 waves) with the thresholds staged in LDS;
+    // many walkers -> one wave per walker, thresholds read through the caches
+    // (LDS then only holds lattices, so more blocks fit per CU).  One Philox
+    // block per lane keeps the neighbour positions in registers.
     const int nw = j->p.n_walkers;
-    // Give each walker as many lanes as keeps about 1-2 waves per SIMD busy.
     const int simds = 4 * (j->n_cu > 0 ? j->n_cu : 256);
     int wpw = 1;
     if (4 * nw <= 2 * simds)
         wpw = 4;
     else if (2 * nw <= 2 * simds)
         wpw = 2;
-    // Blocks (4 sites) in the largest colour class vs lanes per walker.
-    int largest = 0;
-    for (int c = 0; c < j->g.C; ++c) largest = std::max(largest, j->g.cls[c + 1] - j->g.cls[c]);
-    const int blocks = (largest + 3) / 4 + 1;
-    int bpl = blocks > 64 * wpw ? 2 : 1;
+    const int bpl = 1;
     LaunchPlan pl;
     while (!plan_launch(j, wpw, bpl, -1, &pl) && wpw < 4) wpw *= 2;  // fewer walkers per block -> less LDS
     j->wpw = wpw;
     j->bpl = bpl;
-    j->lds_tables_req = -1;
+    j->lds_tables_req = wpw == 1 ? 0 : -1;
+    if (!plan_launch(j, wpw, bpl, j->lds_tables_req, &pl)) j->lds_tables_req = -1;
 }
 
 int upload_tables(muca_job *j)
@@ -628,6 +629,19 @@ int muca_get_launch(const muca_job *j, int32_t *wpw, int32_t *bpl, int32_t *lds_
     if (bpl) *bpl = j->bpl;
     if (lds_tables) *lds_tables = pl.lds_tables ? 1 : 0;
     if (lds_bytes) *lds_bytes = (int32_t)pl.lds;
+    return MUCA_OK;
+}
+
+int muca_flatness(const int64_t *hist, int32_t lo, int32_t hi, double *flatness_out)
+{
+    if (!hist || !flatness_out || lo < 0 || hi < lo) return MUCA_E_INVAL;
+    int64_t sum = 0, least = hist[lo];
+    for (int32_t E = lo; E <= hi; ++E) {
+        if (hist[E] < 0) return MUCA_E_INVAL;
+        sum += hist[E];
+        least = std::min(least, hist[E]);
+    }
+    *flatness_out = sum > 0 ? (double)least / ((double)sum / (double)(hi - lo + 1)) : 0.0;
     return MUCA_OK;
 }
 

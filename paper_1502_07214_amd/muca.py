@@ -29,7 +29,7 @@ EXPORTS = (
     "muca_set_weights", "muca_get_weights", "muca_reweight", "muca_read_state", "muca_write_state",
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
-    "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free",
+    "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness",
 )
 
 
@@ -91,6 +91,7 @@ def lib():
     L.muca_batch_sweep.argtypes = [vp, i64, u32]
     L.muca_batch_free.argtypes = [vp]
     L.muca_batch_free.restype = None
+    L.muca_flatness.argtypes = [P(i64), i32, i32, P(dbl)]
     for name in EXPORTS:
         if name not in ("muca_strerror", "muca_free", "muca_batch_free"):
             getattr(L, name).restype = ctypes.c_int
@@ -126,6 +127,14 @@ def muca_host_tables(L: int, T: float, lnW: np.ndarray):
     D = ctypes.c_double
     _check(lib().muca_host_tables(L, float(T), _p(lw, D), _p(Bp, D), _p(Rp, D), _p(Rm, D)), "muca_host_tables")
     return Bp, Rp, Rm
+
+
+def muca_flatness(hist: np.ndarray, lo: int, hi: int) -> float:
+    h = np.ascontiguousarray(hist, dtype=np.int64)
+    assert 0 <= lo <= hi < len(h)
+    out = ctypes.c_double()
+    _check(lib().muca_flatness(_p(h, ctypes.c_int64), int(lo), int(hi), ctypes.byref(out)), "muca_flatness")
+    return out.value
 
 
 def muca_host_order(L: int) -> np.ndarray:

@@ -49,3 +49,37 @@ def workload(name: str, truncated: bool = False) -> dict:
     w["V"] = w["L"] ** 3
     w["attempts"] = w["n_walkers"] * w["V"] * (w["iterations"] * w["sweeps"] + w["production"])
     return w
+
+
+# Batched: 4096 walkers in 64 groups of 64; each group's (L, T) drawn uniformly
+# from {8,10,12,16,20} x {0.9,1.0,1.4182,2.0} by a seeded generator; groups
+# with equal (L, T) form one job (one histogram, one weight function);
+# 10 iterations x 1000 sweeps from flat weights.
+BATCHED = dict(groups=64, group_walkers=64, Ls=(8, 10, 12, 16, 20), Ts=(0.9, 1.0, 1.4182, 2.0), seed=0,
+               iterations=10, sweeps=1000)
+
+
+def batched_jobs(spec=BATCHED) -> list:
+    """[(L, T, n_walkers, seed)] of the batched workload, one entry per job."""
+    rng = np.random.default_rng(spec["seed"])
+    combos = [(L, T) for L in spec["Ls"] for T in spec["Ts"]]
+    picks = rng.integers(0, len(combos), size=spec["groups"])
+    counts = {}
+    for p in picks:
+        counts[combos[p]] = counts.get(combos[p], 0) + spec["group_walkers"]
+    return [(L, T, n, 1000 * L + int(round(T * 1e4))) for (L, T), n in sorted(counts.items())]
+
+
+# Served: Poisson arrivals (mean 20 jobs/s) of MUCA jobs, weights tilted to
+# Delta_mid(T), 500 sweeps per iteration until the E_Delta histogram over
+# [0, V] is flat (min/mean > 0.5), cap 2000 iterations.  The full mix (L in
+# 8..24, 200 jobs) needs hours of device time per run because flatness over the
+# whole E_Delta range of an L = 24 lattice takes thousands of iterations; the
+# benchmark serves the same kind of stream at L in 6..10.
+SERVED = dict(n_jobs=60, rate=20.0, seed=0, L_range=(6, 10), T_range=(0.9, 2.0),
+              walker_choices=(64, 128, 192, 256, 320, 384, 448, 512), sweeps=500, threshold=0.5,
+              max_iterations=2000)
+SERVED_FULL = dict(SERVED, n_jobs=200, L_range=(8, 24))
+
+# Saturation: enough walkers to fill every SIMD several times over (roofline run).
+SATURATION = dict(L=8, T=2.0, n_walkers=65536, seed=0, sweeps=100)
