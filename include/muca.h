@@ -80,7 +80,7 @@ typedef struct {
     void *hist;         /* V+1 uint64: E_Delta histogram of the current iteration */
     void *tables;       /* thresholds B'[25], R_-/R_+[V+1], lnW[V+1], neighbour and site tables */
     void *accum;        /* 7 x (V+1) uint64 per-bin production sums: H, SJ, SJJ, S|M|, SM2, SM4 lo, SM4 hi */
-    void *obs;          /* reweighting scratch: max_delta x (1 + MUCA_N_OBS) doubles */
+    void *obs;          /* reweighting scratch: Delta values, observables, ln P(E_Delta), per-bin sums */
 } muca_dev_buffers;
 
 /* Observables of one reweighting point (Sec. II; Eqs. (FieldDerivative), (sph)). */
@@ -153,6 +153,21 @@ int muca_get_weights(const muca_job *job, double *lnW_out);
  * device block per Delta.  n_delta in 1..max_delta.  MUCA_E_STATE when nothing
  * has been recorded.  Synchronises. */
 int muca_reweight(muca_job *job, const double *delta, int32_t n_delta, muca_obs *out);
+
+/* Reweighting of caller-supplied per-bin sums (e.g. a jackknife subset of the
+ * production measurements, Sec. II-III): sums (5 x (V+1) int64: H, SJ, SJJ,
+ * S|M|, SM2) and sm4 (2 x (V+1) uint64: low, high words of the 128-bit sums of
+ * M^4), recorded under the job's current weights.  Otherwise as muca_reweight.
+ * MUCA_E_STATE if sums holds no measurement.  Synchronises. */
+int muca_reweight_sums(muca_job *job, const int64_t *sums, const uint64_t *sm4, const double *delta,
+                       int32_t n_delta, muca_obs *out);
+
+/* Reweighted distribution of E_Delta at (beta, delta) from the production
+ * histogram and the weights it was recorded under (Sec. II: the measurements
+ * of bin E carry weight exp(-beta delta E) / W(E)): lnP_out[E] = ln P(E) for
+ * E = 0..V, normalised to sum 1, -INFINITY where nothing was recorded.  One
+ * device block.  MUCA_E_STATE when nothing has been recorded.  Synchronises. */
+int muca_reweight_hist(muca_job *job, double delta, double *lnP_out);
 
 /* Copy walker state to the host: spins (n_walkers x V int8, site-indexed
  * i = x + L(y + Lz), may be NULL) and state (n_walkers x 4 int64: E_J, E_Delta,

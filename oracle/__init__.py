@@ -257,3 +257,94 @@ def reweight(V: int, beta: float, lnW, sums: Dict[str, list], deltas) -> np.ndar
                   -beta * cov, beta * beta * third, beta * beta * var_e / V,
                   np.sum(p * mA), m2, m4, u4, edge)
     return out
+
+
+# --------------------------------------------------------------------------
+# Analysis on top of reweighting (Sec. II-III): the pseudo-critical point
+# Delta*_L (maximum of C(Delta), found by bisection on the zero of dC/dDelta),
+# jackknife errors over w subsets each leaving out 1/w of the measurements,
+# the reweighted distribution of e_Delta, the equal-height field and the barrier.
+# --------------------------------------------------------------------------
+def _col(name):
+    return OBS_FIELDS.index(name)
+
+
+def peak(V: int, beta: float, lnW, sums, lo: float, hi: float, tol: float = 1e-11):
+    """(Delta*, C*) with Delta* in [lo, hi] where dC/dDelta changes sign from
+    + to -; bisection until the bracket is narrower than tol."""
+    dc = lambda d: reweight(V, beta, lnW, sums, [d])[0, _col("dC_dDelta")]
+    flo, fhi = dc(lo), dc(hi)
+    if not (flo > 0 and fhi < 0):
+        raise ValueError("dC/dDelta does not change sign from + to - on the bracket")
+    while hi - lo > tol:
+        mid = 0.5 * (lo + hi)
+        if dc(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    d = 0.5 * (lo + hi)
+    return d, float(reweight(V, beta, lnW, sums, [d])[0, _col("C_field")])
+
+
+def block_sums_difference(total: dict, part: dict) -> dict:
+    """Per-bin sums of all measurements except those in `part` (exact integers)."""
+    return {k: ([a - b for a, b in zip(total[k], part[k])] if k != "V" else total[k]) for k in total}
+
+
+def add_sums(a: dict, b: dict) -> dict:
+    return {k: ([x + y for x, y in zip(a[k], b[k])] if k != "V" else a[k]) for k in a}
+
+
+def jackknife(values) -> tuple:
+    """Jackknife mean and error of leave-one-block-out estimates (Efron)."""
+    v = np.asarray(values, dtype=np.float64)
+    w = len(v)
+    m = v.mean()
+    return float(m), float(math.sqrt((w - 1) / w * np.sum((v - m) ** 2)))
+
+
+def reweighted_log_hist(V: int, beta: float, lnW, H, delta: float) -> np.ndarray:
+    """ln P(E_Delta) at (beta, Delta) from the recorded histogram H: the
+    measurements of bin E carry weight exp(-beta Delta E) / W(E); -inf where
+    nothing was recorded.  Normalised to sum 1."""
+    H = np.asarray([float(h) for h in H])
+    E = np.arange(V + 1, dtype=np.float64)
+    out = np.full(V + 1, -np.inf)
+    seen = H > 0
+    a = -(beta * delta) * E[seen] - np.asarray(lnW, dtype=np.float64)[seen] + np.log(H[seen])
+    amax = a.max()
+    out[seen] = a - (amax + math.log(np.sum(np.exp(a - amax))))
+    return out
+
+
+def two_peaks(lnP: np.ndarray, split: int) -> tuple:
+    """(E_low, lnP_low, E_high, lnP_high): the maxima of lnP on [0, split) and
+    [split, V]."""
+    lo = int(np.argmax(lnP[:split]))
+    hi = split + int(np.argmax(lnP[split:]))
+    return lo, float(lnP[lo]), hi, float(lnP[hi])
+
+
+def equal_height(V: int, beta: float, lnW, H, lo: float, hi: float, split: int, tol: float = 1e-11):
+    """Delta_eqh in [lo, hi] where the two peaks of P(e_Delta) (maxima below and
+    above the bin `split`) have equal height, by bisection on their log ratio
+    (which decreases as Delta grows: larger Delta favours small E_Delta), and the
+    barrier B = ln(P_max / P_min) / (2 beta Delta_eqh), P_min the minimum of P
+    between the two peaks."""
+    def diff(d):
+        _, a, _, b = two_peaks(reweighted_log_hist(V, beta, lnW, H, d), split)
+        return b - a
+    if not (diff(lo) > 0 and diff(hi) < 0):
+        raise ValueError("peak heights do not cross on the bracket")
+    while hi - lo > tol:
+        mid = 0.5 * (lo + hi)
+        if diff(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    d = 0.5 * (lo + hi)
+    lnP = reweighted_log_hist(V, beta, lnW, H, d)
+    e1, p1, e2, p2 = two_peaks(lnP, split)
+    pmin = float(np.min(lnP[e1:e2 + 1]))
+    barrier = (max(p1, p2) - pmin) / (2.0 * beta * d) if beta > 0 and d != 0 else float("nan")
+    return d, barrier

@@ -1,0 +1,111 @@
+"""Analysis of a multicanonical production run (Sec. II-III of the paper).
+
+* Pseudo-critical point: Delta*_L maximises C(Delta) = d<E_J>/dDelta; it is
+  located by bisection on the zero of dC/dDelta (the second field derivative of
+  <E_J>), each evaluation a reweighting on the device.  C*_L = C(Delta*_L).
+* Jackknife: the production run is recorded in w consecutive time blocks; the
+  estimate is repeated on the w subsets that each leave one block out, and the
+  error is sqrt((w-1)/w sum (x_j - mean)^2).
+* Equal-height field: the Delta where the two peaks of the reweighted P(e_Delta)
+  (maxima below and above a split bin) have equal height; the barrier
+  ln(P_max / P_min) / (2 beta Delta_eqh) uses the minimum of P between them.
+
+Every reweighting runs in libmuca (muca_reweight, muca_reweight_sums,
+muca_reweight_hist); this module only drives the searches.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Tuple
+
+import numpy as np
+
+from .muca import OBS_FIELDS, MucaJob
+
+_DC = OBS_FIELDS.index("dC_dDelta")
+_C = OBS_FIELDS.index("C_field")
+
+
+def _reweight(job: MucaJob, sums, d: float) -> np.ndarray:
+    return (job.reweight([d]) if sums is None else job.reweight_sums(sums, [d]))[0]
+
+
+def peak(job: MucaJob, lo: float, hi: float, tol: float = 1e-11, sums=None) -> Tuple[float, float]:
+    """(Delta*, C*) in [lo, hi]; dC/dDelta must go from + at lo to - at hi."""
+    f_lo, f_hi = _reweight(job, sums, lo)[_DC], _reweight(job, sums, hi)[_DC]
+    if not (f_lo > 0 and f_hi < 0):
+        raise ValueError("dC/dDelta does not change sign from + to - on the bracket")
+    while hi - lo > tol:
+        mid = 0.5 * (lo + hi)
+        if _reweight(job, sums, mid)[_DC] > 0:
+            lo = mid
+        else:
+            hi = mid
+    d = 0.5 * (lo + hi)
+    return d, float(_reweight(job, sums, d)[_C])
+
+
+def _zero_sums(V: int) -> dict:
+    return {k: [0] * (V + 1) for k in ("H", "SJ", "SJJ", "SA", "SM2", "SM4")} | {"V": V}
+
+
+def _minus(a: dict, b: dict) -> dict:
+    return {k: ([x - y for x, y in zip(a[k], b[k])] if k != "V" else a[k]) for k in a}
+
+
+def production_blocks(job: MucaJob, n_blocks: int, sweeps: int) -> Tuple[List[dict], dict]:
+    """Record n_blocks consecutive production segments of `sweeps` sweeps;
+    return the per-block per-bin sums and their total (exact integers)."""
+    job.reset_accum()
+    prev = _zero_sums(job.V)
+    blocks = []
+    for _ in range(n_blocks):
+        job.sweep(sweeps, record=True)
+        cur = job.read_accum()
+        blocks.append(_minus(cur, prev))
+        prev = cur
+    return blocks, prev
+
+
+def jackknife(values) -> Tuple[float, float]:
+    v = np.asarray(values, dtype=np.float64)
+    w = len(v)
+    m = float(v.mean())
+    return m, float(math.sqrt((w - 1) / w * np.sum((v - m) ** 2)))
+
+
+def jackknife_peak(job: MucaJob, blocks: List[dict], total: dict, lo: float, hi: float, tol: float = 1e-11):
+    """Delta*, C* on all measurements, with jackknife errors over the blocks."""
+    d, c = peak(job, lo, hi, tol, sums=total)
+    loo = [peak(job, lo, hi, tol, sums=_minus(total, b)) for b in blocks]
+    dj, de = jackknife([x[0] for x in loo])
+    cj, ce = jackknife([x[1] for x in loo])
+    return {"delta_star": d, "C_star": c, "delta_star_err": de, "C_star_err": ce,
+            "delta_star_jk_mean": dj, "C_star_jk_mean": cj, "blocks": len(blocks)}
+
+
+def _peaks(lnP: np.ndarray, split: int):
+    a = int(np.argmax(lnP[:split]))
+    b = split + int(np.argmax(lnP[split:]))
+    return a, float(lnP[a]), b, float(lnP[b])
+
+
+def equal_height(job: MucaJob, lo: float, hi: float, split: int, tol: float = 1e-11) -> Tuple[float, float]:
+    """(Delta_eqh, barrier) with Delta_eqh in [lo, hi]."""
+    def diff(d):
+        _, a, _, b = _peaks(job.reweight_hist(d), split)
+        return b - a
+    if not (diff(lo) > 0 and diff(hi) < 0):
+        raise ValueError("peak heights do not cross on the bracket")
+    while hi - lo > tol:
+        mid = 0.5 * (lo + hi)
+        if diff(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    d = 0.5 * (lo + hi)
+    lnP = job.reweight_hist(d)
+    e1, p1, e2, p2 = _peaks(lnP, split)
+    pmin = float(np.min(lnP[e1:e2 + 1]))
+    barrier = (max(p1, p2) - pmin) / (2.0 * job.beta * d) if job.beta > 0 and d != 0 else float("nan")
+    return d, barrier

@@ -97,8 +97,9 @@ Layout make_layout(const muca_params *p)
     g.off_site = g.off_nb + align_up((size_t)12 * g.Vp, 256);
     g.tables_bytes = g.off_site + align_up((size_t)2 * g.Vp, 256);
     g.accum_bytes = align_up(7 * 8 * V1, 256);
-    g.obs_bytes = align_up((size_t)g.max_delta * (1 + MUCA_N_OBS) * 8, 256);
-    if (g.obs_bytes == 0) g.obs_bytes = 256;
+    g.off_obs_lnp = align_up((size_t)g.max_delta * (1 + MUCA_N_OBS) * 8, 256);
+    g.off_obs_sums = g.off_obs_lnp + align_up(8 * V1, 256);
+    g.obs_bytes = g.off_obs_sums + align_up(7 * 8 * V1, 256);
     return g;
 }
 
@@ -486,21 +487,16 @@ int muca_get_weights(const muca_job *j, double *lnW_out)
     return MUCA_OK;
 }
 
-int muca_reweight(muca_job *j, const double *delta, int32_t n_delta, muca_obs *out)
+static int reweight_from(muca_job *j, const unsigned long long *acc_dev, const double *delta, int32_t n_delta,
+                         muca_obs *out)
 {
-    if (!j || !delta || !out || n_delta < 1) return MUCA_E_INVAL;
-    if (n_delta > j->g.max_delta) return MUCA_E_SIZE;
-    for (int k = 0; k < n_delta; ++k)
-        if (!std::isfinite(delta[k])) return MUCA_E_INVAL;
-    if (j->recorded <= 0) return MUCA_E_STATE;
-    if (int rc = use_device(j)) return rc;
     const Layout &g = j->g;
     double *pd = reinterpret_cast<double *>(j->pin_obs);
     std::memcpy(pd, delta, sizeof(double) * n_delta);
     double *dobs = reinterpret_cast<double *>(j->d.obs);
     HIP_TRY(hipMemcpyAsync(dobs, pd, sizeof(double) * n_delta, hipMemcpyHostToDevice, j->stream));
     ReweightArgs a;
-    a.acc = reinterpret_cast<const unsigned long long *>(j->d.accum);
+    a.acc = acc_dev;
     a.lnw = reinterpret_cast<const double *>(reinterpret_cast<unsigned char *>(j->d.tables) + g.off_lnw);
     a.delta = dobs;
     a.obs = dobs + g.max_delta;
@@ -511,6 +507,56 @@ int muca_reweight(muca_job *j, const double *delta, int32_t n_delta, muca_obs *o
                            hipMemcpyDeviceToHost, j->stream));
     HIP_TRY(hipStreamSynchronize(j->stream));
     std::memcpy(out, pd + g.max_delta, sizeof(double) * MUCA_N_OBS * n_delta);
+    return MUCA_OK;
+}
+
+int muca_reweight(muca_job *j, const double *delta, int32_t n_delta, muca_obs *out)
+{
+    if (!j || !delta || !out || n_delta < 1) return MUCA_E_INVAL;
+    if (n_delta > j->g.max_delta) return MUCA_E_SIZE;
+    for (int k = 0; k < n_delta; ++k)
+        if (!std::isfinite(delta[k])) return MUCA_E_INVAL;
+    if (j->recorded <= 0) return MUCA_E_STATE;
+    if (int rc = use_device(j)) return rc;
+    return reweight_from(j, reinterpret_cast<const unsigned long long *>(j->d.accum), delta, n_delta, out);
+}
+
+int muca_reweight_sums(muca_job *j, const int64_t *sums, const uint64_t *sm4, const double *delta, int32_t n_delta,
+                       muca_obs *out)
+{
+    if (!j || !sums || !sm4 || !delta || !out || n_delta < 1) return MUCA_E_INVAL;
+    if (n_delta > j->g.max_delta) return MUCA_E_SIZE;
+    for (int k = 0; k < n_delta; ++k)
+        if (!std::isfinite(delta[k])) return MUCA_E_INVAL;
+    const size_t V1 = (size_t)j->g.V + 1;
+    int64_t n = 0;
+    for (size_t E = 0; E < V1; ++E) {
+        if (sums[E] < 0) return MUCA_E_INVAL;
+        n += sums[E];
+    }
+    if (n == 0) return MUCA_E_STATE;
+    if (int rc = use_device(j)) return rc;
+    unsigned char *scratch = reinterpret_cast<unsigned char *>(j->d.obs) + j->g.off_obs_sums;
+    HIP_TRY(hipMemcpyAsync(scratch, sums, 5 * V1 * 8, hipMemcpyHostToDevice, j->stream));
+    HIP_TRY(hipMemcpyAsync(scratch + 5 * V1 * 8, sm4, 2 * V1 * 8, hipMemcpyHostToDevice, j->stream));
+    return reweight_from(j, reinterpret_cast<const unsigned long long *>(scratch), delta, n_delta, out);
+}
+
+int muca_reweight_hist(muca_job *j, double delta, double *lnP_out)
+{
+    if (!j || !lnP_out || !std::isfinite(delta)) return MUCA_E_INVAL;
+    if (j->recorded <= 0) return MUCA_E_STATE;
+    if (int rc = use_device(j)) return rc;
+    const Layout &g = j->g;
+    LogHistArgs a;
+    a.hist = reinterpret_cast<const unsigned long long *>(j->d.accum);  // production counts H
+    a.lnw = reinterpret_cast<const double *>(reinterpret_cast<unsigned char *>(j->d.tables) + g.off_lnw);
+    a.lnp = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(j->d.obs) + g.off_obs_lnp);
+    a.V = g.V;
+    a.bd = j->beta * delta;
+    HIP_TRY(launch_log_hist(a, j->stream));
+    HIP_TRY(hipMemcpyAsync(lnP_out, a.lnp, sizeof(double) * (g.V + 1), hipMemcpyDeviceToHost, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
     return MUCA_OK;
 }
 

@@ -25,6 +25,7 @@ struct Layout {
     int n_walkers, max_delta;
     size_t lattice_bytes, state_bytes, hist_bytes, tables_bytes, accum_bytes, obs_bytes;
     size_t off_bp, off_r, off_lnw, off_nb, off_site;  // byte offsets inside tables
+    size_t off_obs_lnp, off_obs_sums;                 // byte offsets inside obs
 };
 
 // Arguments of the sweep kernel.
@@ -56,6 +57,14 @@ struct InitArgs {
     const uint16_t *site;
     int V, Vp, n_walkers;
     uint32_t k0, k1;
+};
+
+struct LogHistArgs {
+    const unsigned long long *hist;  // V+1 counts
+    const double *lnw;               // V+1
+    double *lnp;                     // V+1 output
+    int V;
+    double bd;                       // beta * Delta
 };
 
 struct ReweightArgs {
@@ -97,6 +106,7 @@ hipError_t launch_sweep(const SweepArgs &a, int waves_per_walker, int blocks_per
                         bool lds_tables, size_t lds_bytes, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s);
+hipError_t launch_log_hist(const LogHistArgs &a, hipStream_t s);
 // blocks <= 0: as many blocks as fit on the device at once
 hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, size_t lds, int blocks, hipStream_t s);
 

@@ -709,6 +709,34 @@ __global__ __launch_bounds__(kBlock) void muca_reweight_kernel(ReweightArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Reweighted ln P(E_Delta) at one Delta (one block): a(E) = -beta Delta E -
+// lnW(E) + ln H(E) over the recorded bins, normalised by a log-sum-exp.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void muca_log_hist_kernel(LogHistArgs a)
+{
+    __shared__ double sh[1][kBlock];
+    const int V = a.V;
+    double amax = -INFINITY;
+    for (int e = threadIdx.x; e <= V; e += kBlock)
+        if (a.hist[e] > 0) amax = fmax(amax, -a.bd * (double)e - a.lnw[e] + log((double)a.hist[e]));
+    sh[0][threadIdx.x] = amax;
+    __syncthreads();
+    for (int half = kBlock / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + half]);
+        __syncthreads();
+    }
+    amax = sh[0][0];
+    __syncthreads();
+    double z[1] = {0.0};
+    for (int e = threadIdx.x; e <= V; e += kBlock)
+        if (a.hist[e] > 0) z[0] += exp(-a.bd * (double)e - a.lnw[e] + log((double)a.hist[e]) - amax);
+    block_sum<1>(z, sh);
+    const double lz = amax + log(z[0]);
+    for (int e = threadIdx.x; e <= V; e += kBlock)
+        a.lnp[e] = a.hist[e] > 0 ? -a.bd * (double)e - a.lnw[e] + log((double)a.hist[e]) - lz : -INFINITY;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_init(const InitArgs &a, hipStream_t s)
@@ -729,6 +757,12 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(muca_zero_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s,
                        reinterpret_cast<uint4 *>(p), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_hist(const LogHistArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(muca_log_hist_kernel, dim3(1), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

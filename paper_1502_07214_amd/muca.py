@@ -29,7 +29,8 @@ EXPORTS = (
     "muca_set_weights", "muca_get_weights", "muca_reweight", "muca_read_state", "muca_write_state",
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
-    "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness",
+    "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
+    "muca_reweight_hist",
 )
 
 
@@ -92,6 +93,8 @@ def lib():
     L.muca_batch_free.argtypes = [vp]
     L.muca_batch_free.restype = None
     L.muca_flatness.argtypes = [P(i64), i32, i32, P(dbl)]
+    L.muca_reweight_sums.argtypes = [vp, P(i64), P(ctypes.c_uint64), P(dbl), i32, P(dbl)]
+    L.muca_reweight_hist.argtypes = [vp, dbl, P(dbl)]
     for name in EXPORTS:
         if name not in ("muca_strerror", "muca_free", "muca_batch_free"):
             getattr(L, name).restype = ctypes.c_int
@@ -204,6 +207,25 @@ class MucaJob:
         out = np.zeros((len(d), len(OBS_FIELDS)))
         _check(lib().muca_reweight(self._h, _p(d, ctypes.c_double), len(d), _p(out, ctypes.c_double)),
                "muca_reweight")
+        return out
+
+    def reweight_sums(self, sums: dict, deltas) -> np.ndarray:
+        """Reweight per-bin sums given as exact integers (the read_accum format)."""
+        V1 = self.V + 1
+        s5 = np.array([[int(v) for v in sums[k]] for k in ("H", "SJ", "SJJ", "SA", "SM2")], dtype=np.int64)
+        m4 = [int(v) for v in sums["SM4"]]
+        sm4 = np.array([[v & 0xFFFFFFFFFFFFFFFF for v in m4], [v >> 64 for v in m4]], dtype=np.uint64)
+        assert s5.shape == (5, V1)
+        d = np.ascontiguousarray(deltas, dtype=np.float64)
+        out = np.zeros((len(d), len(OBS_FIELDS)))
+        _check(lib().muca_reweight_sums(self._h, _p(s5, ctypes.c_int64), _p(sm4, ctypes.c_uint64),
+                                        _p(d, ctypes.c_double), len(d), _p(out, ctypes.c_double)), "muca_reweight_sums")
+        return out
+
+    def reweight_hist(self, delta: float) -> np.ndarray:
+        """ln P(E_Delta) at Delta from the production histogram."""
+        out = np.zeros(self.V + 1)
+        _check(lib().muca_reweight_hist(self._h, float(delta), _p(out, ctypes.c_double)), "muca_reweight_hist")
         return out
 
     # -- weights, state, accumulators ---------------------------------------

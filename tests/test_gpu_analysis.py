@@ -1,0 +1,91 @@
+"""Analysis on the GPU path vs the oracle on the same (bit-identical) chains:
+reweighted ln P(E_Delta), the peak of C(Delta) with jackknife errors over time
+blocks, and the equal-height field with its barrier."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_07214_amd import MucaJob, analysis
+
+pytestmark = pytest.mark.gpu
+
+
+def make_pair(L, T, nw, seed, iterations, sweeps, lnW=None):
+    job = MucaJob(L, T, nw, seed=seed, lnW=lnW, max_delta=4)
+    o = oracle.OracleJob(L, T, nw, seed, lnW=lnW)
+    for _ in range(iterations):
+        job.sweep(sweeps)
+        job.update_weights(job.reduce_hist())
+        o.sweep(sweeps)
+        o.update_weights(o.take_hist())
+    assert job.lnW.tobytes() == o.lnW.tobytes()
+    return job, o
+
+
+def oracle_blocks(o, n_blocks, sweeps):
+    o.reset_accum()
+    prev = {k: [0] * (o.V + 1) for k in ("H", "SJ", "SJJ", "SA", "SM2", "SM4")} | {"V": o.V}
+    blocks = []
+    for _ in range(n_blocks):
+        o.sweep(sweeps, record=True)
+        cur = o.bin_sums()
+        blocks.append(oracle.block_sums_difference(cur, prev))
+        prev = cur
+    return blocks, prev
+
+
+def test_peak_and_jackknife_match_oracle():
+    L, T = 4, 1.4182
+    print(f"[analysis] peak L={L} T={T}", flush=True)
+    job, o = make_pair(L, T, 16, 21, 8, 1000)
+    blocks, total = analysis.production_blocks(job, 4, 1000)
+    oblocks, ototal = oracle_blocks(o, 4, 1000)
+    assert total == ototal and blocks == oblocks
+    # bracket the maximum of C from a scan of the oracle
+    grid = np.linspace(1.5, 4.0, 126)
+    cs = oracle.reweight(o.V, o.beta, o.lnW, ototal, grid)[:, oracle.OBS_FIELDS.index("C_field")]
+    k = int(np.argmax(cs))
+    lo, hi = grid[max(k - 2, 0)], grid[min(k + 2, len(grid) - 1)]
+    d_o, c_o = oracle.peak(o.V, o.beta, o.lnW, ototal, lo, hi)
+    d_g, c_g = analysis.peak(job, lo, hi, sums=total)
+    assert abs(d_g - d_o) < 1e-9 and abs(c_g - c_o) < 1e-10 * abs(c_o)
+    jk = analysis.jackknife_peak(job, blocks, total, lo, hi)
+    loo = [oracle.peak(o.V, o.beta, o.lnW, oracle.block_sums_difference(ototal, b), lo, hi) for b in oblocks]
+    dm, de = oracle.jackknife([x[0] for x in loo])
+    cm, ce = oracle.jackknife([x[1] for x in loo])
+    assert abs(jk["delta_star"] - d_o) < 1e-9
+    assert abs(jk["delta_star_err"] - de) < 1e-8 * max(de, 1e-3)
+    assert abs(jk["C_star_err"] - ce) < 1e-8 * max(ce, 1e-3)
+    # the device reweighting of the job's own sums agrees with the sums path
+    assert np.array_equal(job.reweight([d_g]), job.reweight_sums(total, [d_g]))
+    job.free()
+
+
+def test_log_hist_and_equal_height_match_oracle():
+    L, T = 4, 1.0
+    print(f"[analysis] equal height L={L} T={T}", flush=True)
+    # start tilted towards the transition field Delta* = 2.944 the paper gives at T = 1
+    job, o = make_pair(L, T, 16, 22, 10, 1000, lnW=-(1.0 / T) * 2.944 * np.arange(L ** 3 + 1))
+    job.reset_accum()
+    job.sweep(3000, record=True)
+    o.reset_accum()
+    o.sweep(3000, record=True)
+    H = o.bin_sums()["H"]
+    for d in (2.5, 2.9, 3.1):
+        g = job.reweight_hist(d)
+        r = oracle.reweighted_log_hist(o.V, o.beta, o.lnW, H, d)
+        fin = np.isfinite(r)
+        assert np.array_equal(fin, np.isfinite(g))
+        assert np.all(np.abs(g[fin] - r[fin]) <= 1e-12 * np.maximum(1.0, np.abs(r[fin])))
+    split = o.V // 2
+    grid = np.linspace(2.0, 4.0, 81)
+    diffs = []
+    for d in grid:
+        _, a, _, b = oracle.two_peaks(oracle.reweighted_log_hist(o.V, o.beta, o.lnW, H, d), split)
+        diffs.append(b - a)
+    k = next(i for i in range(len(grid) - 1) if diffs[i] > 0 and diffs[i + 1] < 0)
+    d_o, b_o = oracle.equal_height(o.V, o.beta, o.lnW, H, grid[k], grid[k + 1], split)
+    d_g, b_g = analysis.equal_height(job, grid[k], grid[k + 1], split)
+    assert abs(d_g - d_o) < 1e-9
+    assert abs(b_g - b_o) < 1e-9 * max(1.0, abs(b_o))
+    job.free()

@@ -385,3 +385,52 @@ def test_muca_pipeline_l2_matches_enumeration():
         assert abs(r[col["mean_ED"]] - ex["mean_ED"]) < 0.1
         assert abs(r[col["C_field"]] - ex["C_field"]) < 0.08 * max(1.0, abs(ex["C_field"]))
         assert abs(r[col["mean_M2"]] - ex["mean_M2"]) < 0.05 * max(1.0, ex["mean_M2"])
+
+
+# --------------------------------------------------------------------------
+# Analysis: peak of C(Delta), jackknife, equal height (Sec. II-III)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("T", [1.0, 1.6])
+def test_peak_of_C_matches_dense_exact_scan(T):
+    beta = 1.0 / T
+    lnW = -l2_exact.ln_g_beta(beta)
+    sums = l2_exact.muca_bin_sums(beta, lnW)
+    d, c = oracle.peak(8, beta, lnW, sums, 2.0, 4.0)
+    grid = np.linspace(2.0, 4.0, 4001)
+    cs = np.array([l2_exact.canonical(beta, x)["C_field"] for x in grid])
+    k = int(np.argmax(cs))
+    assert abs(d - grid[k]) < 1e-3
+    assert abs(c - cs[k]) < 1e-6 * abs(cs[k])
+    # C is the derivative of <E_J>: at the peak, dC/dDelta vanishes
+    assert abs(l2_exact.canonical(beta, d)["dC_dDelta"]) < 1e-6
+
+
+@pytest.mark.parametrize("T", [0.2, 0.25, 0.3])
+def test_equal_height_zero_temperature(T):
+    """Two peaks at E_Delta = 0 (all vacancies) and V (no vacancies, degeneracy
+    2 at T -> 0): equal height at Delta_0 + T ln 2 / V with Delta_0 = 3 (Sec. I)."""
+    beta = 1.0 / T
+    lnW = -l2_exact.ln_g_beta(beta)
+    sums = l2_exact.muca_bin_sums(beta, lnW, n=1.0)
+    d, barrier = oracle.equal_height(8, beta, lnW, sums["H"], 2.5, 3.5, split=4)
+    assert abs(d - (3.0 + T * math.log(2.0) / 8)) < T * math.exp(-3.0 * beta)
+    assert barrier > 0
+
+
+def test_reweighted_log_hist_is_exact_canonical_marginal():
+    beta, delta = 1.0 / 1.3, 2.7
+    lnW = np.random.default_rng(1).normal(0, 1.0, 9)
+    sums = l2_exact.muca_bin_sums(beta, lnW)
+    lnP = oracle.reweighted_log_hist(8, beta, lnW, sums["H"], delta)
+    e = l2_exact.EJ + delta * l2_exact.ED
+    w = np.exp(-beta * (e - e.min()))
+    exact = np.array([w[l2_exact.ED == E].sum() for E in range(9)]) / w.sum()
+    assert np.allclose(np.exp(lnP), exact, rtol=1e-12, atol=0)
+
+
+def test_jackknife_of_a_linear_statistic_is_the_standard_error():
+    x = np.random.default_rng(2).normal(size=20)
+    loo = [(x.sum() - xi) / 19 for xi in x]
+    m, e = oracle.jackknife(loo)
+    assert abs(m - x.mean()) < 1e-12
+    assert abs(e - x.std(ddof=1) / math.sqrt(20)) < 1e-12
