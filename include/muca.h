@@ -205,9 +205,10 @@ int muca_get_launch(const muca_job *job, int32_t *waves_per_walker, int32_t *blo
  * and accepted moves.  Off by default; a few atomics per pass. */
 int muca_set_stats(muca_job *job, int32_t enable);
 
-/* out[0] = passes, out[1] = fixed-point rounds, out[2] = accepted moves, summed
- * over walkers since the last reset (3 int64).  reset != 0 zeroes them
- * afterwards.  Synchronises. */
+/* out[0] = passes, out[1] = fixed-point decision rounds (summed over the
+ * waves that share a walker), out[2] = accepted moves, summed over walkers
+ * since the last reset (3 int64).  reset != 0 zeroes them afterwards.
+ * Synchronises. */
 int muca_read_stats(muca_job *job, int64_t *out, int32_t reset);
 
 /* ---------------------------------------------------------------------------

@@ -13,7 +13,9 @@
 //    guesses the E_Delta it will see, decides, a walker-wide prefix sum of the
 //    accepted E_Delta steps gives new guesses, and the loop stops when no guess
 //    changes.  Iteration k fixes at least the first k sites of the chain, so it
-//    ends after at most (sites in the pass + 1) rounds; in practice 2-4.
+//    ends after at most (sites in the pass + 1) rounds.  When several waves
+//    share a walker, each wave iterates its own chunk without barriers and
+//    the waves exchange only chunk totals between such inner iterations.
 //  * Lattices live in LDS as one int8 per site in colour-major position order;
 //    a lane owns 4 consecutive positions (one Philox block) per group, so spin
 //    writes are whole dwords with no atomics.  Thresholds B', R_+-, and the
@@ -75,8 +77,9 @@ struct Walker {
     int V, wave, lane, slot, wi, lg;
     uint32_t w32, k0, k1;
     int ED;                              // E_Delta of the walker (uniform)
+    int parity;                          // exchange buffer in use (alternates)
     unsigned myEJ, myM;                  // this lane's accepted E_J and M changes (mod 2^32)
-    unsigned rounds, accepted;           // diagnostics of the last pass
+    unsigned rounds, accepted;           // diagnostics of the last pass (this wave)
 
     // nq[q][dir]: neighbour positions of the 4 sites of block q (two per uint2).
     __device__ __forceinline__ void pass(int P0, int P1, int jbase, uint32_t sweep, const uint2 (&nq)[BPL][6],
@@ -124,12 +127,21 @@ struct Walker {
         // ---- sequential part: exact fixed point over E_Delta ----
         // Per site: sens = the decision depends on E_Delta (valid, d != 0),
         // ridx = 0 for R_-, 1 for R_+.  Branch-free: every site does the same
-        // work, all threshold loads of a round are issued together, and the
-        // loop exit is wave-uniform.  Round 0 decides every site at the
-        // walker's E_Delta; round t decides each site at the E_Delta implied
-        // by the decisions of round t-1 before it (a prefix sum over the
-        // walker's lanes).  Round t reproduces at least the first t sites of
-        // the sequential chain, so the rounds stop at the chain's own result.
+        // work, all threshold loads of a round are issued together, and loop
+        // exits are wave-uniform.  Round 0 decides every site at the walker's
+        // E_Delta.  A later round decides each site at the E_Delta implied by
+        // the previous decisions of the sites before it (a prefix sum); round t
+        // reproduces at least the first t sites of the sequential chain, so
+        // the rounds stop at the chain's own result.
+        //
+        // With several waves per walker the iteration is two-level.  Each wave
+        // iterates its own chunk of the pass to a fixed point, wave-locally and
+        // without barriers, from an assumed E_Delta at the chunk's start; the
+        // waves then exchange chunk totals once (one barrier), which gives every
+        // chunk a new start.  The walker is done when no start changes: every
+        // chunk then holds the exact chain from the exact E_Delta before it.
+        // Chunk 0 always starts right, so after k exchanges the first k chunks
+        // do, and at most WPW + 1 exchanges happen (the first one after round 0).
         int sens[NS], ridx[NS], vmask[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -140,22 +152,63 @@ struct Walker {
         int Eg[NS];
         int acci[NS];
         int ex[NS];
-        int total = 0;
-        int changedPrev = 1;  // did the previous round change any guess (round -1: yes)
-        int parity = 0;
-        const int cap = GL * NS + 3;
-        int it = 0;
         {
             const double rm = R[2 * ED], rpl = R[2 * ED + 1];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                Eg[k] = ED;
                 const double f = dd[k] == 0 ? 1.0 : (ridx[k] ? rpl : rm);
                 acci[k] = (u[k] < bp[k] * f ? 1 : 0) & vmask[k];
             }
         }
-        for (;; ++it) {
-            if (it > 0) {
+        int laneOff, wtot;
+        auto scan = [&]() {
+            int run = 0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                ex[k] = run;
+                run += dd[k] & -acci[k];
+            }
+            const unsigned incl = wave_incl_sum((unsigned)run);
+            laneOff = (int)incl - run;
+            wtot = (int)wave_total(incl);
+        };
+        // Exchange of chunk totals: start offsets (relative to the walker's
+        // E_Delta) of all four waves of the block, and the walkers' totals.
+        int off[4] = {0, 0, 0, 0};
+        int wsum = 0;
+        auto exchange = [&](int (&no)[4]) {
+            if (lane == 63) sX[4 * parity + wave] = wtot;
+            __syncthreads();
+            const int4 xw = *reinterpret_cast<const int4 *>(sX + 4 * parity);
+            parity ^= 1;
+            const int xs[4] = {xw.x, xw.y, xw.z, xw.w};
+            int before = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (v % WPW == 0) before = 0;
+                no[v] = before;
+                before += xs[v];
+                if (v / WPW == slot) wsum = before;
+            }
+        };
+        scan();
+        if (WPW > 1) exchange(off);
+        int waveOff = off[wave];
+        int changed = 0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int ne = ED + waveOff + laneOff + ex[k];
+            changed |= (ne != ED ? 1 : 0) & sens[k];
+            Eg[k] = ne;
+        }
+        bool again = __ballot(changed) != 0ull;
+        unsigned nround = 1;
+        int outer = 0;
+        const int cap = 64 * NS + 2;
+        for (;;) {
+            // wave-local fixed point of this chunk from start ED + waveOff
+            int inner = 0;
+            while (again) {
                 double r[NS];
 #pragma unroll
                 for (int k = 0; k < NS; ++k) r[k] = R[2 * min(max(Eg[k], 0), V) + ridx[k]];
@@ -164,65 +217,46 @@ struct Walker {
                     const double f = dd[k] == 0 ? 1.0 : r[k];
                     acci[k] = (u[k] < bp[k] * f ? 1 : 0) & vmask[k];
                 }
-            }
-            int run = 0;
+                scan();
+                changed = 0;
 #pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                ex[k] = run;
-                run += dd[k] & -acci[k];
-            }
-            const unsigned incl = wave_incl_sum((unsigned)run);
-            const int laneOff = (int)incl - run;
-            int waveOff = 0;
-            int wtotal = (int)wave_total(incl);
-            if (WPW > 1) {
-                // one exchange per round: this round's wave total together with
-                // the previous round's "guesses changed" flag
-                if (lane == 63) sX[4 * parity + wave] = (int)((unsigned)wtotal << 1) | changedPrev;
-                __syncthreads();
-                const int4 xw = *reinterpret_cast<const int4 *>(sX + 4 * parity);
-                const int xs[4] = {xw.x, xw.y, xw.z, xw.w};
-                int before = 0, sum = 0, flag = 0;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    flag |= xs[v] & 1;
-                    const int tv = xs[v] >> 1;
-                    const bool mine = (v / WPW) == slot;
-                    before += (mine && (v % WPW) < wi) ? tv : 0;
-                    sum += mine ? tv : 0;
+                for (int k = 0; k < NS; ++k) {
+                    const int ne = ED + waveOff + laneOff + ex[k];
+                    changed |= (ne != Eg[k] ? 1 : 0) & sens[k];
+                    Eg[k] = ne;
                 }
-                waveOff = before;
-                wtotal = sum;
-                parity ^= 1;
-                // the guesses of this round equal those of the previous one,
-                // which reproduced themselves: this is the fixed point
-                if (__builtin_amdgcn_readfirstlane(flag) == 0) {
-                    total = wtotal;
-                    break;
+                again = __ballot(changed) != 0ull;
+                ++nround;
+                if (++inner > cap) {
+                    if (lane == 0) atomicOr(err, 1);
+                    again = false;
                 }
             }
-            int changed = 0;
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                const int ne = ED + waveOff + laneOff + ex[k];
-                changed |= (ne != Eg[k] ? 1 : 0) & sens[k];
-                Eg[k] = ne;
-            }
-            changedPrev = __ballot(changed) != 0ull ? 1 : 0;
-            if (WPW == 1 && changedPrev == 0) {
-                total = wtotal;
+            if (WPW == 1) {
+                wsum = wtot;
                 break;
             }
-            if (it >= cap) {
+            int no[4];
+            exchange(no);
+            const bool stable = no[0] == off[0] && no[1] == off[1] && no[2] == off[2] && no[3] == off[3];
+            if (stable) break;  // block-uniform: every wave read the same words
+            if (++outer > WPW) {
                 if (lane == 0) atomicOr(err, 1);
-                total = wtotal;
                 break;
             }
+            const int shift = no[wave] - waveOff;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) off[v] = no[v];
+            waveOff = off[wave];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Eg[k] += shift;
+            again = shift != 0;
         }
+        const int total = wsum;
         bool acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = acci[k] != 0;
-        rounds = (unsigned)(it + 1);
+        rounds = nround;
         // ---- apply the accepted moves ----
         unsigned nacc = 0;
 #pragma unroll
@@ -313,6 +347,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
         sweep = (uint32_t)st.w;
     }
     if (tid < 8) sX[tid] = 0;
+    wk.parity = 0;
     wk.lat = lat;
     wk.R = R;
     wk.sBp = sBp;
@@ -347,10 +382,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
             const unsigned n = wave_total(wave_incl_sum(wk.accepted));
             if (live && lane == 0) {
                 atomicAdd(&a.stats[2], (unsigned long long)n);
-                if (lg == 0) {
-                    atomicAdd(&a.stats[0], 1ull);
-                    atomicAdd(&a.stats[1], (unsigned long long)wk.rounds);
-                }
+                atomicAdd(&a.stats[1], (unsigned long long)wk.rounds);
+                if (lg == 0) atomicAdd(&a.stats[0], 1ull);
             }
         }
     };
