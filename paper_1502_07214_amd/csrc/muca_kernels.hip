@@ -55,6 +55,14 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// min(max(x, 0), hi) in one instruction.
+__device__ __forceinline__ int clamp0(int x, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+
 // Proposal: the b-th (ascending) of the two spin values other than s.
 __device__ __forceinline__ int propose(int s, int b)
 {
@@ -92,21 +100,40 @@ struct Walker {
         double u[NS], bp[NS];
         int dd[NS], dej[NS], dsg[NS], snew[NS], sold[NS];
         bool valid[NS];
+        // spins first: their LDS latency overlaps the generator's rounds
+        int words[BPL];
+        int nbs[BPL][6][4];
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int jb = jb0 + q;
+            const int jbc = jb < j1 ? jb : j0;
+            words[q] = *reinterpret_cast<const int *>(lat + 4 * jbc);
+#pragma unroll
+            for (int dir = 0; dir < 6; ++dir) {
+                nbs[q][dir][0] = lat[nq[q][dir].x & 0xffffu];
+                nbs[q][dir][1] = lat[nq[q][dir].x >> 16];
+                nbs[q][dir][2] = lat[nq[q][dir].y & 0xffffu];
+                nbs[q][dir][3] = lat[nq[q][dir].y >> 16];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // the round keys are cheap to rebuild; keeping them live across
+        // passes would only spill them
+        uint32_t kk0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k0);
+        uint32_t kk1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k1);
+        asm volatile("" : "+s"(kk0), "+s"(kk1));
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
             const int jb = jb0 + q;
             const bool blk = jb < j1;
             const int jbc = blk ? jb : j0;
-            const Ctr4 x = philox10((uint32_t)jbc, w32, sweep, 0u, k0, k1);
-            const int word = *reinterpret_cast<const int *>(lat + 4 * jbc);
+            const Ctr4 x = philox10((uint32_t)jbc, w32, sweep, 0u, kk0, kk1);
+            const int word = words[q];
             int h[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int dir = 0; dir < 6; ++dir) {
-                h[0] += lat[nq[q][dir].x & 0xffffu];
-                h[1] += lat[nq[q][dir].x >> 16];
-                h[2] += lat[nq[q][dir].y & 0xffffu];
-                h[3] += lat[nq[q][dir].y >> 16];
-            }
+            for (int dir = 0; dir < 6; ++dir)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) h[t] += nbs[q][dir][t];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int k = 4 * q + t;
@@ -125,14 +152,16 @@ struct Walker {
             }
         }
         // ---- sequential part: exact fixed point over E_Delta ----
-        // Per site: sens = the decision depends on E_Delta (valid, d != 0),
-        // ridx = 0 for R_-, 1 for R_+.  Branch-free: every site does the same
-        // work, all threshold loads of a round are issued together, and loop
-        // exits are wave-uniform.  Round 0 decides every site at the walker's
-        // E_Delta.  A later round decides each site at the E_Delta implied by
-        // the previous decisions of the sites before it (a prefix sum); round t
-        // reproduces at least the first t sites of the sequential chain, so
-        // the rounds stop at the chain's own result.
+        // Round 0 decides every site at the walker's E_Delta.  A later round
+        // decides each site at the E_Delta implied by the previous decisions of
+        // the sites before it (a prefix sum); round t reproduces at least the
+        // first t sites of the sequential chain, so the rounds stop at the
+        // chain's own result.  Every site does the same work (all threshold
+        // loads of a round issue together) and loop exits are wave-uniform.
+        // A round's decisions are kept as wave masks (one bit per lane and
+        // site): the guesses are a fixed point exactly when no decision that
+        // moves E_Delta (a valid site with d != 0) differs from the previous
+        // round's, so the test is scalar and needs no guess comparison.
         //
         // With several waves per walker the iteration is two-level.  Each wave
         // iterates its own chunk of the pass to a fixed point, wave-locally and
@@ -142,42 +171,59 @@ struct Walker {
         // chunk then holds the exact chain from the exact E_Delta before it.
         // Chunk 0 always starts right, so after k exchanges the first k chunks
         // do, and at most WPW + 1 exchanges happen (the first one after round 0).
-        int sens[NS], ridx[NS], vmask[NS];
+        int ddv[NS], ridx[NS];
+        bool acc0[NS];
+        uint64_t SENS[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            sens[k] = (valid[k] && dd[k] != 0) ? 1 : 0;
-            ridx[k] = dd[k] > 0 ? 1 : 0;
-            vmask[k] = valid[k] ? 1 : 0;
+            ddv[k] = valid[k] ? dd[k] : 0;   // E_Delta step if accepted
+            ridx[k] = dd[k] > 0 ? 1 : 0;     // 0: R_-, 1: R_+
+            acc0[k] = valid[k] && u[k] < bp[k];  // the decision where d == 0
+            SENS[k] = __ballot(ddv[k] != 0);
         }
-        int Eg[NS];
-        int acci[NS];
-        int ex[NS];
+        bool c[NS];      // this lane's decisions of the last round
+        uint64_t S[NS];  // the same as wave masks
         {
             const double rm = R[2 * ED], rpl = R[2 * ED + 1];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const double f = dd[k] == 0 ? 1.0 : (ridx[k] ? rpl : rm);
-                acci[k] = (u[k] < bp[k] * f ? 1 : 0) & vmask[k];
+                c[k] = u[k] < bp[k] * (ridx[k] ? rpl : rm);
+                S[k] = __ballot(c[k]);
             }
         }
-        int laneOff, wtot;
+        int ex[NS];
+        int laneOff;
+        unsigned incl;
         auto scan = [&]() {
             int run = 0;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
                 ex[k] = run;
-                run += dd[k] & -acci[k];
+                run += c[k] ? ddv[k] : 0;
             }
-            const unsigned incl = wave_incl_sum((unsigned)run);
+            incl = wave_incl_sum((unsigned)run);
             laneOff = (int)incl - run;
-            wtot = (int)wave_total(incl);
         };
         // Exchange of chunk totals: start offsets (relative to the walker's
         // E_Delta) of all four waves of the block, and the walkers' totals.
         int off[4] = {0, 0, 0, 0};
         int wsum = 0;
+        auto write_spins = [&]() {
+#pragma unroll
+            for (int q = 0; q < BPL; ++q) {
+                const int jb = jb0 + q;
+                unsigned nw = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 4 * q + t;
+                    const bool a = ddv[k] != 0 ? c[k] : acc0[k];
+                    nw |= ((unsigned)(a ? snew[k] : sold[k]) & 0xffu) << (8 * t);
+                }
+                if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
+            }
+        };
         auto exchange = [&](int (&no)[4]) {
-            if (lane == 63) sX[4 * parity + wave] = wtot;
+            if (lane == 63) sX[4 * parity + wave] = (int)incl;
             __syncthreads();
             const int4 xw = *reinterpret_cast<const int4 *>(sX + 4 * parity);
             parity ^= 1;
@@ -193,47 +239,46 @@ struct Walker {
         };
         scan();
         if (WPW > 1) exchange(off);
-        int waveOff = off[wave];
-        int changed = 0;
+        int base = ED + off[wave];
+        int Eg[NS];
+        uint64_t moved = 0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const int ne = ED + waveOff + laneOff + ex[k];
-            changed |= (ne != ED ? 1 : 0) & sens[k];
-            Eg[k] = ne;
+            Eg[k] = base + laneOff + ex[k];
+            moved |= __ballot(Eg[k] != ED) & SENS[k];
         }
-        bool again = __ballot(changed) != 0ull;
+        // round 0 decided at E_Delta itself: done unless a guess moved
+        bool again = moved != 0;
         unsigned nround = 1;
         int outer = 0;
         const int cap = 64 * NS + 2;
         for (;;) {
-            // wave-local fixed point of this chunk from start ED + waveOff
+            // wave-local fixed point of this chunk from the start `base`
             int inner = 0;
             while (again) {
                 double r[NS];
 #pragma unroll
-                for (int k = 0; k < NS; ++k) r[k] = R[2 * min(max(Eg[k], 0), V) + ridx[k]];
+                for (int k = 0; k < NS; ++k) r[k] = R[2 * clamp0(Eg[k], V) + ridx[k]];
+                uint64_t diff = 0;
 #pragma unroll
                 for (int k = 0; k < NS; ++k) {
-                    const double f = dd[k] == 0 ? 1.0 : r[k];
-                    acci[k] = (u[k] < bp[k] * f ? 1 : 0) & vmask[k];
+                    c[k] = u[k] < bp[k] * r[k];
+                    const uint64_t m = __ballot(c[k]);
+                    diff |= (m ^ S[k]) & SENS[k];
+                    S[k] = m;
                 }
-                scan();
-                changed = 0;
-#pragma unroll
-                for (int k = 0; k < NS; ++k) {
-                    const int ne = ED + waveOff + laneOff + ex[k];
-                    changed |= (ne != Eg[k] ? 1 : 0) & sens[k];
-                    Eg[k] = ne;
-                }
-                again = __ballot(changed) != 0ull;
                 ++nround;
+                if (diff == 0) break;
+                scan();
+#pragma unroll
+                for (int k = 0; k < NS; ++k) Eg[k] = base + laneOff + ex[k];
                 if (++inner > cap) {
                     if (lane == 0) atomicOr(err, 1);
-                    again = false;
+                    break;
                 }
             }
             if (WPW == 1) {
-                wsum = wtot;
+                wsum = (int)wave_total(incl);
                 break;
             }
             int no[4];
@@ -244,10 +289,10 @@ struct Walker {
                 if (lane == 0) atomicOr(err, 1);
                 break;
             }
-            const int shift = no[wave] - waveOff;
+            const int shift = no[wave] - off[wave];
 #pragma unroll
             for (int v = 0; v < 4; ++v) off[v] = no[v];
-            waveOff = off[wave];
+            base += shift;
 #pragma unroll
             for (int k = 0; k < NS; ++k) Eg[k] += shift;
             again = shift != 0;
@@ -255,24 +300,16 @@ struct Walker {
         const int total = wsum;
         bool acc[NS];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] = acci[k] != 0;
+        for (int k = 0; k < NS; ++k) acc[k] = ddv[k] != 0 ? c[k] : acc0[k];
         rounds = nround;
         // ---- apply the accepted moves ----
+        write_spins();
         unsigned nacc = 0;
 #pragma unroll
-        for (int q = 0; q < BPL; ++q) {
-            const int jb = jb0 + q;
-            unsigned nw = 0;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = 4 * q + t;
-                const int v = acc[k] ? snew[k] : sold[k];
-                nw |= ((unsigned)v & 0xffu) << (8 * t);
-                myEJ += acc[k] ? (unsigned)dej[k] : 0u;
-                myM += acc[k] ? (unsigned)dsg[k] : 0u;
-                nacc += acc[k] ? 1u : 0u;
-            }
-            if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
+        for (int k = 0; k < NS; ++k) {
+            myEJ += acc[k] ? (unsigned)dej[k] : 0u;
+            myM += acc[k] ? (unsigned)dsg[k] : 0u;
+            nacc += acc[k] ? 1u : 0u;
         }
         accepted = nacc;
         ED += total;

@@ -15,6 +15,14 @@ struct Ctr4 {
     uint32_t v[4];
 };
 
+// a ^ b ^ c in one instruction (three-input bitwise op of gfx950, truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 __device__ __forceinline__ Ctr4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t key0, uint32_t key1)
 {
@@ -26,8 +34,8 @@ __device__ __forceinline__ Ctr4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
         const uint32_t kb = key1 + weylB * (uint32_t)round;
         const uint64_t pa = (uint64_t)mulA * c0;
         const uint64_t pb = (uint64_t)mulB * c2;
-        const uint32_t t0 = (uint32_t)(pb >> 32) ^ c1 ^ ka;
-        const uint32_t t2 = (uint32_t)(pa >> 32) ^ c3 ^ kb;
+        const uint32_t t0 = xor3((uint32_t)(pb >> 32), c1, ka);
+        const uint32_t t2 = xor3((uint32_t)(pa >> 32), c3, kb);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = t0;
