@@ -235,6 +235,13 @@ void default_launch(muca_job *j)
     j->wpw = wpw;
     j->bpl = bpl;
     j->lds_tables_req = wpw == 1 ? 0 : -1;
+    if (wpw > 1 && plan_launch(j, wpw, bpl, 1, &pl) && pl.lds_tables) {
+        // staged tables only while every block still fits on the device at
+        // once: a second wave of blocks costs more than the cached reads
+        const long blocks = (nw + 4 / wpw - 1) / (4 / wpw);
+        const long per_cu = std::max<long>(1, (long)j->max_lds / (long)pl.lds);
+        if (blocks > per_cu * (long)(simds / 4)) j->lds_tables_req = 0;
+    }
     if (!plan_launch(j, wpw, bpl, j->lds_tables_req, &pl)) j->lds_tables_req = -1;
 }
 

@@ -289,7 +289,7 @@ struct Walker {
                 if (lane == 0) atomicOr(err, 1);
                 break;
             }
-            const int shift = no[wave] - off[wave];
+            const int shift = __builtin_amdgcn_readfirstlane(no[wave] - off[wave]);
 #pragma unroll
             for (int v = 0; v < 4; ++v) off[v] = no[v];
             base += shift;
@@ -338,7 +338,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     const int V = a.V, Vp = a.Vp;
     const int tid = threadIdx.x;
     W wk;
-    wk.wave = tid >> 6;
+    wk.wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: say so
     wk.lane = tid & 63;
     wk.slot = wk.wave / WPW;
     wk.wi = wk.wave % WPW;
