@@ -28,19 +28,21 @@ METRIC = "spin-flip attempts/sec on 1 GPU (plain vs batched/served) + p99 time-t
 WORKLOAD = "l12_t2_w256"
 
 # Algorithmic VALU issue slots per attempt (one site visit), counted from what
-# the method must compute: a quarter of a Philox4x32-10 block (10 rounds of two
-# 32x32->64 products at 4 slots per 32-bit multiply half and 4 XORs) = 50; the
-# six-neighbour sum 5; proposal 4; dS, dE_J, dE_Delta 5; u31 to double 3; the
-# threshold product and compare (FP64, 2 slots each) 4; E_J/E_Delta/M updates 3;
-# the spin write-back select 1.
-ALGO_SLOTS_PER_ATTEMPT = 75
+# the method must compute, in full-rate lane slots (a full-rate wave64 VALU
+# instruction = 64 lane slots; instruction costs measured on MI355X: v_xor_b32,
+# v_mul_f64, v_cvt_f64_u32 full rate, v_mad_u64_u32 1.5x):
+#   a quarter of a Philox4x32-10 block: 5 32x32->64 products (7.5) and 5
+#   three-input XORs (5) = 12.5; six-neighbour sum 3; proposal 3; dS, dE_J,
+#   dE_Delta 4; u31 to double 2; B' index 1; FP64 threshold product and compare
+#   2; E_J/E_Delta/M updates 3; spin write-back select 1; class/validity 1.
+ALGO_SLOTS_PER_ATTEMPT = 32.5
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate VALU lane slots.
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # HBM bytes per 10^4-sweep launch of muca_sweep_kernel<4,1,false,true,2> on this
 # workload: FETCH_SIZE + WRITE_SIZE from rocprofv3, each scaled by the same
 # counter's reading on a plain 1 GiB copy (profiles/sweep_kernel_l12_t2_w256_pmc.txt).
 TRAFFIC_KERNEL = "muca_sweep_kernel<4, 1, false, true, 2>"
-TRAFFIC_BYTES_PER_LAUNCH = 1834702
+TRAFFIC_BYTES_PER_LAUNCH = 1889996
 
 
 def parse():
