@@ -15,6 +15,7 @@ the algorithmic VALU work per attempt (see ALGO_SLOTS_PER_ATTEMPT).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -43,6 +44,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # counter's reading on a plain 1 GiB copy (profiles/sweep_kernel_l12_t2_w256_pmc.txt).
 TRAFFIC_KERNEL = "muca_sweep_kernel<4, 1, false, true, 2>"
 TRAFFIC_BYTES_PER_LAUNCH = 1889996
+# weight recursions of the convergence legs (flags of muca_set_recursion)
+REC_EXTRAPOLATE, REC_ACC_EXT = 2, 3
 
 
 def parse():
@@ -52,7 +55,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, served and saturation legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, saturation, served and convergence legs")
     ap.add_argument("--launch", default=None, help="wpw,bpl,lds_tables (default: library's choice)")
     return ap.parse_args()
 
@@ -131,11 +134,45 @@ def served_leg():
     sp = workloads.SERVED
     reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"])
     cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"])
+    fast = dataclasses.replace(cfg, recursion=REC_EXTRAPOLATE)
     out = {"spec": {k: v for k, v in sp.items()}}
-    for mode, fn in (("served", serve), ("plain", serve_plain)):
-        r = fn(reqs, cfg)
+    for mode, fn, c in (("served", serve, cfg), ("plain", serve_plain, cfg), ("served_extrapolating", serve, fast)):
+        r = fn(reqs, c)
         out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "makespan_s", "jobs_per_s", "attempts_per_s",
                                        "latency_p50_s", "latency_p99_s", "iterations_p50", "queue_depth_max")}
+    return out
+
+
+def convergence_leg():
+    """Iterations and seconds to a flat histogram (F > 0.5 over [0, V]) for
+    single jobs: the plain recursion, edge extrapolation, and accumulated pair
+    statistics with extrapolation, from a flat and from a tilted start."""
+    import torch
+
+    from paper_1502_07214_amd import MucaJob, workloads
+    from paper_1502_07214_amd.serve import tilted_weights
+
+    out = []
+    for c in workloads.CONVERGENCE:
+        for start in ("flat", "tilted"):
+            for name, flags in (("plain", 0), ("extrapolate", REC_EXTRAPOLATE), ("accumulated+extrapolate", REC_ACC_EXT)):
+                lnW = tilted_weights(c["L"], c["T"]) if start == "tilted" else None
+                job = MucaJob(c["L"], c["T"], c["n_walkers"], seed=c["seed"], lnW=lnW, max_delta=1)
+                job.set_recursion(flags)
+                t0 = time.perf_counter()
+                it, f = 0, 0.0
+                while it < c["max_iterations"]:
+                    job.sweep(c["sweeps"])
+                    h = job.reduce_hist()
+                    it += 1
+                    f = job.update_weights(h)
+                    if f > c["threshold"]:
+                        break
+                torch.cuda.synchronize()
+                out.append({"L": c["L"], "T": c["T"], "walkers": c["n_walkers"], "sweeps": c["sweeps"],
+                            "start": start, "recursion": name, "iterations": it, "flat": f > c["threshold"],
+                            "seconds": time.perf_counter() - t0})
+                job.free()
     return out
 
 
@@ -253,6 +290,8 @@ def main():
         out["saturation"] = saturation_leg()
         print("[bench] served leg", file=sys.stderr, flush=True)
         out["served"] = served_leg()
+        print("[bench] convergence leg", file=sys.stderr, flush=True)
+        out["convergence"] = convergence_leg()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, deltas)

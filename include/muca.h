@@ -131,13 +131,32 @@ int muca_sweep(muca_job *job, int64_t n_sweeps, uint32_t flags);
 int muca_reduce_hist(muca_job *job, int64_t *hist_host, int32_t reset);
 
 /* Step "update" (Sec. II, iterative weights): lnW[E] -= log(H[E]) where H[E] > 0
- * (plain recursion W <- W / H) on the job's weights, then re-upload the
+ * (plain recursion W <- W / H; muca_set_recursion selects a variant) on the
+ * job's weights, then re-upload the
  * threshold tables.  hist (V+1, non-negative) is the merged histogram of the
  * iteration; lnW_out (V+1, may be NULL) receives the new weights; flatness_out
  * (may be NULL) receives min_E H[E] / mean_E H[E] over [0, V] of hist.  The
  * production sums are cleared (they belong to the weights they were sampled
  * under).  Host FP64; the upload is asynchronous. */
 int muca_update_weights(muca_job *job, const int64_t *hist, double *lnW_out, double *flatness_out);
+
+/* Weight recursion used by muca_update_weights from now on (flags below; 0,
+ * the default, is the plain recursion W <- W / H on the visited bins).  The
+ * paper adapts W iteratively and cites the multicanonical recursions of Berg
+ * and of Janke without printing one (Sec. II); these are the variants:
+ *   MUCA_REC_ACCUMULATED: the log-weight differences d(E) = lnW(E+1) - lnW(E)
+ *     take the mean of every iteration's estimate d(E) + ln H(E) - ln H(E+1),
+ *     weighted by its inverse Poisson variance H(E)H(E+1)/(H(E)+H(E+1)); a
+ *     pair with one visited bin takes the plain step; lnW(0) is kept and the
+ *     rest rebuilt from the differences.
+ *   MUCA_REC_EXTRAPOLATE: bins outside the range visited in any iteration so
+ *     far continue the mean slope of the last min(8, width) differences inside
+ *     it, at each end.
+ * Resets the accumulated statistics and the visited range.  MUCA_E_INVAL on
+ * unknown flags.  Host only. */
+#define MUCA_REC_ACCUMULATED 1u
+#define MUCA_REC_EXTRAPOLATE 2u
+int muca_set_recursion(muca_job *job, uint32_t flags);
 
 /* Replace the job's weights by lnW (V+1 finite doubles) and re-upload the
  * thresholds; clears the production sums.  For weights carried over from an

@@ -80,6 +80,8 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_update_weights.argtypes = [ctypes.c_int, i64p, dp]
         L.orc_update_weights.restype = ctypes.c_double
+        L.orc_update_weights_ex.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_uint, dp, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_update_weights_ex.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -162,6 +164,15 @@ class OracleJob:
         self.hist = np.zeros(self.V + 1, dtype=np.int64)
         self.reset_accum()
         self.threads_used = 0
+        self.set_recursion(0)
+
+    def set_recursion(self, flags: int):
+        """Weight recursion from now on: 0 plain, bit 0 accumulated pair
+        statistics, bit 1 edge extrapolation (orc_update_weights_ex).  Clears
+        the accumulated statistics and the visited range."""
+        self.recursion = int(flags)
+        self.kacc = np.zeros(max(self.V, 1), dtype=np.float64)
+        self.seen = np.zeros(self.V + 1, dtype=np.uint8)
 
     def reset_accum(self):
         self.acc = np.zeros((5, self.V + 1), dtype=np.int64)
@@ -182,9 +193,15 @@ class OracleJob:
         return h
 
     def update_weights(self, hist: np.ndarray) -> float:
-        """Plain MUCA recursion on self.lnW; returns the flatness of hist."""
+        """MUCA recursion on self.lnW (plain unless set_recursion chose a
+        variant); returns the flatness of hist."""
         h = np.ascontiguousarray(hist, dtype=np.int64)
-        return float(lib().orc_update_weights(self.V, _ptr(h, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double)))
+        if self.recursion == 0:
+            self.seen |= (h > 0).astype(np.uint8)
+            return float(lib().orc_update_weights(self.V, _ptr(h, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double)))
+        return float(lib().orc_update_weights_ex(self.V, _ptr(h, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double),
+                                                 self.recursion, _ptr(self.kacc, ctypes.c_double),
+                                                 _ptr(self.seen, ctypes.c_uint8)))
 
     def bin_sums(self) -> Dict[str, list]:
         """Per-bin sums of the recorded measurements as exact Python integers."""

@@ -369,3 +369,82 @@ double orc_update_weights(int V, const int64_t *hist, double *lnW)
         return 0.0;
     return (double)least / ((double)total / (double)(V + 1));
 }
+
+/* ------------------------------------------------------------------------ */
+/* Faster weight convergence (the recursion variants the paper cites, after  */
+/* Berg's multicanonical recursion as presented by Janke; not printed in the */
+/* paper, so the exact form below is this implementation's reading).         */
+/*                                                                          */
+/* flags & 1 (accumulated): the log-weight differences d(E) = lnW(E+1) -     */
+/*   lnW(E) of neighbouring bins are updated with the statistics of every    */
+/*   iteration so far, each iteration weighted by its significance           */
+/*   k_n(E) = H(E) H(E+1) / (H(E) + H(E+1)):                                 */
+/*     K(E) += k_n(E);  d(E) += (k_n(E) / K(E)) * (log H(E) - log H(E+1))   */
+/*   for pairs with both bins visited.  A pair with one bin visited takes the */
+/*   plain step (the empty side counts as one entry); a pair with none keeps  */
+/*   d.  The weights are rebuilt from d upwards from bin 0, whose value is    */
+/*   kept.  With K starting at 0 the first iteration is the plain recursion.  */
+/* flags & 2 (extrapolate): bins outside the range [lo, hi] of bins visited  */
+/*   in any iteration so far continue the slope of lnW over the last         */
+/*   k = min(8, hi - lo) bins inside the range, at each end.                  */
+/* kacc (V doubles) and seen (V+1 bytes) carry the state between iterations. */
+/* Returns the flatness of hist as orc_update_weights does.                   */
+/* ------------------------------------------------------------------------ */
+double orc_update_weights_ex(int V, const int64_t *hist, double *lnW, unsigned flags, double *kacc,
+                             uint8_t *seen)
+{
+    int64_t total = 0, least = hist[0];
+    for (int E = 0; E <= V; E++) {
+        total += hist[E];
+        if (hist[E] < least)
+            least = hist[E];
+        if (hist[E] > 0)
+            seen[E] = 1;
+    }
+    if (flags & 1u) {
+        double *d = (double *)malloc(sizeof(double) * (size_t)(V > 0 ? V : 1));
+        for (int E = 0; E < V; E++)
+            d[E] = lnW[E + 1] - lnW[E];
+        for (int E = 0; E < V; E++) {
+            int64_t a = hist[E], b = hist[E + 1];
+            if (a > 0 && b > 0) {
+                double ha = (double)a, hb = (double)b;
+                double k = ha * hb / (ha + hb);
+                kacc[E] = kacc[E] + k;
+                d[E] = d[E] + (k / kacc[E]) * (log(ha) - log(hb));
+            } else if (a > 0) {
+                d[E] = d[E] + log((double)a);
+            } else if (b > 0) {
+                d[E] = d[E] - log((double)b);
+            }
+        }
+        for (int E = 0; E < V; E++)
+            lnW[E + 1] = lnW[E] + d[E];
+        free(d);
+    } else {
+        for (int E = 0; E <= V; E++)
+            if (hist[E] > 0)
+                lnW[E] = lnW[E] - log((double)hist[E]);
+    }
+    if (flags & 2u) {
+        int lo = -1, hi = -1;
+        for (int E = 0; E <= V; E++)
+            if (seen[E]) {
+                if (lo < 0)
+                    lo = E;
+                hi = E;
+            }
+        if (lo >= 0 && hi > lo) {
+            int k = hi - lo < 8 ? hi - lo : 8;
+            double s_hi = (lnW[hi] - lnW[hi - k]) / (double)k;
+            double s_lo = (lnW[lo + k] - lnW[lo]) / (double)k;
+            for (int E = hi + 1; E <= V; E++)
+                lnW[E] = lnW[hi] + (double)(E - hi) * s_hi;
+            for (int E = lo - 1; E >= 0; E--)
+                lnW[E] = lnW[lo] - (double)(lo - E) * s_lo;
+        }
+    }
+    if (total == 0)
+        return 0.0;
+    return (double)least / ((double)total / (double)(V + 1));
+}

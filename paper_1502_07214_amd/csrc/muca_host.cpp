@@ -140,6 +140,11 @@ struct muca_job {
     muca_dev_buffers d;
     std::vector<int> order;   // position -> site
     std::vector<double> lnW;  // current weights (V+1)
+    // weight recursion: MUCA_REC_* flags, accumulated pair statistics (V),
+    // bins visited in any iteration since the recursion was set (V+1)
+    uint32_t rec_flags;
+    std::vector<double> kacc;
+    std::vector<uint8_t> seen;
     // launch shape
     int wpw, bpl, lds_tables_req;
     // pinned staging
@@ -327,6 +332,9 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
     else
         j->lnW.assign(g.V + 1, 0.0);
     j->recorded = 0;
+    j->rec_flags = 0u;
+    j->kacc.assign(std::max(g.V, 1), 0.0);
+    j->seen.assign(g.V + 1, 0);
 
     auto bail = [&](int rc) {
         muca_free(j);
@@ -456,6 +464,61 @@ int muca_reduce_hist(muca_job *j, int64_t *hist_host, int32_t reset)
     return MUCA_OK;
 }
 
+int muca_set_recursion(muca_job *j, uint32_t flags)
+{
+    if (!j || (flags & ~(MUCA_REC_ACCUMULATED | MUCA_REC_EXTRAPOLATE))) return MUCA_E_INVAL;
+    j->rec_flags = flags;
+    j->kacc.assign(std::max(j->g.V, 1), 0.0);
+    j->seen.assign(j->g.V + 1, 0);
+    return MUCA_OK;
+}
+
+namespace {
+
+// Accumulated recursion on the log-weight differences of neighbouring bins:
+// each iteration's estimate of the flat-histogram difference enters with its
+// inverse Poisson variance k = H(E) H(E+1) / (H(E) + H(E+1)); a pair with one
+// visited bin takes the plain step; the weights are rebuilt upwards from bin 0.
+void accumulated_step(int V, const int64_t *hist, double *lnW, double *kacc)
+{
+    std::vector<double> d(std::max(V, 1));
+    for (int E = 0; E < V; ++E) d[E] = lnW[E + 1] - lnW[E];
+    for (int E = 0; E < V; ++E) {
+        const int64_t a = hist[E], b = hist[E + 1];
+        if (a > 0 && b > 0) {
+            const double ha = (double)a, hb = (double)b;
+            const double k = ha * hb / (ha + hb);
+            kacc[E] = kacc[E] + k;
+            d[E] = d[E] + (k / kacc[E]) * (std::log(ha) - std::log(hb));
+        } else if (a > 0) {
+            d[E] = d[E] + std::log((double)a);
+        } else if (b > 0) {
+            d[E] = d[E] - std::log((double)b);
+        }
+    }
+    for (int E = 0; E < V; ++E) lnW[E + 1] = lnW[E] + d[E];
+}
+
+// Bins outside the visited range [lo, hi] continue the mean slope of the last
+// min(8, hi - lo) differences inside it, at each end.
+void extrapolate_edges(int V, const uint8_t *seen, double *lnW)
+{
+    int lo = -1, hi = -1;
+    for (int E = 0; E <= V; ++E)
+        if (seen[E]) {
+            if (lo < 0) lo = E;
+            hi = E;
+        }
+    if (lo < 0 || hi <= lo) return;
+    const int k = std::min(hi - lo, 8);
+    const double s_hi = (lnW[hi] - lnW[hi - k]) / (double)k;
+    const double s_lo = (lnW[lo + k] - lnW[lo]) / (double)k;
+    for (int E = hi + 1; E <= V; ++E) lnW[E] = lnW[hi] + (double)(E - hi) * s_hi;
+    for (int E = lo - 1; E >= 0; --E) lnW[E] = lnW[lo] - (double)(lo - E) * s_lo;
+}
+
+}  // namespace
+
 int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, double *flatness_out)
 {
     if (!j || !hist) return MUCA_E_INVAL;
@@ -463,13 +526,20 @@ int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, doubl
     for (int E = 0; E <= V; ++E)
         if (hist[E] < 0) return MUCA_E_INVAL;
     if (int rc = use_device(j)) return rc;
-    // W <- W / H on the visited bins (plain multicanonical recursion)
     int64_t sum = 0, least = hist[0];
     for (int E = 0; E <= V; ++E) {
         sum += hist[E];
         least = std::min(least, hist[E]);
-        if (hist[E] > 0) j->lnW[E] = j->lnW[E] - std::log((double)hist[E]);
+        if (hist[E] > 0) j->seen[E] = 1;
     }
+    if (j->rec_flags & MUCA_REC_ACCUMULATED) {
+        accumulated_step(V, hist, j->lnW.data(), j->kacc.data());
+    } else {
+        // W <- W / H on the visited bins (plain multicanonical recursion)
+        for (int E = 0; E <= V; ++E)
+            if (hist[E] > 0) j->lnW[E] = j->lnW[E] - std::log((double)hist[E]);
+    }
+    if (j->rec_flags & MUCA_REC_EXTRAPOLATE) extrapolate_edges(V, j->seen.data(), j->lnW.data());
     if (flatness_out) *flatness_out = sum > 0 ? (double)least / ((double)sum / (double)(V + 1)) : 0.0;
     if (lnW_out) std::memcpy(lnW_out, j->lnW.data(), sizeof(double) * (V + 1));
     if (int rc = upload_tables(j)) return rc;

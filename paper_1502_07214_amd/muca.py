@@ -30,8 +30,12 @@ EXPORTS = (
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
     "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
-    "muca_reweight_hist",
+    "muca_reweight_hist", "muca_set_recursion",
 )
+
+# weight recursion flags (muca_set_recursion)
+REC_ACCUMULATED = 1
+REC_EXTRAPOLATE = 2
 
 
 class MucaError(RuntimeError):
@@ -69,6 +73,7 @@ def lib():
     L.muca_sweep.argtypes = [vp, i64, u32]
     L.muca_reduce_hist.argtypes = [vp, P(i64), i32]
     L.muca_update_weights.argtypes = [vp, P(i64), P(dbl), P(dbl)]
+    L.muca_set_recursion.argtypes = [vp, ctypes.c_uint32]
     L.muca_set_weights.argtypes = [vp, P(dbl)]
     L.muca_get_weights.argtypes = [vp, P(dbl)]
     L.muca_reweight.argtypes = [vp, P(dbl), i32, P(dbl)]
@@ -185,6 +190,7 @@ class MucaJob:
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
         _check(rc, "muca_init")
         self._h = handle
+        self.recursion = 0
 
     # -- the hot path -----------------------------------------------------
     def sweep(self, n_sweeps: int, record: bool = False):
@@ -234,6 +240,12 @@ class MucaJob:
         w = np.zeros(self.V + 1)
         _check(lib().muca_get_weights(self._h, _p(w, ctypes.c_double)), "muca_get_weights")
         return w
+
+    def set_recursion(self, flags: int):
+        """Weight recursion of update_weights from now on (REC_ACCUMULATED,
+        REC_EXTRAPOLATE or 0 for the plain recursion); resets its statistics."""
+        _check(lib().muca_set_recursion(self._h, int(flags)), "muca_set_recursion")
+        self.recursion = int(flags)
 
     def set_weights(self, lnW):
         w = np.ascontiguousarray(lnW, dtype=np.float64)

@@ -96,6 +96,7 @@ class ServeConfig:
     max_walkers: int = 32768       # resident walkers
     hbm_budget: int = 16 << 30     # resident device bytes
     shape: Optional[Tuple[int, int]] = None  # batched launch shape (None: library default)
+    recursion: int = 0             # weight recursion flags (REC_ACCUMULATED | REC_EXTRAPOLATE; 0 plain)
 
 
 class _Live:
@@ -103,6 +104,8 @@ class _Live:
         r = rec.req
         self.rec = rec
         self.job = MucaJob(r.L, r.T, r.n_walkers, seed=r.seed, lnW=tilted_weights(r.L, r.T), max_delta=1)
+        if cfg.recursion:
+            self.job.set_recursion(cfg.recursion)
         self.V = r.L ** 3
         self.lo = int(round(cfg.window[0] * self.V))
         self.hi = int(round(cfg.window[1] * self.V))

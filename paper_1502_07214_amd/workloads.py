@@ -83,3 +83,13 @@ SERVED_FULL = dict(SERVED, n_jobs=200, L_range=(8, 24))
 
 # Saturation: enough walkers to fill every SIMD several times over (roofline run).
 SATURATION = dict(L=8, T=2.0, n_walkers=65536, seed=0, sweeps=100)
+
+# Time to a flat histogram (min/mean > 0.5 over [0, V]) for single jobs, with
+# the plain recursion and with the accumulated + extrapolating one, from a flat
+# start and from the start tilted towards the transition field.  With the plain
+# recursion from a flat start, L = 12 needs at least
+# (3 beta V + ln 2) / ln(walkers x sweeps) ~ 200 iterations at these sizes.
+CONVERGENCE = (
+    dict(L=8, T=2.0, n_walkers=256, seed=0, sweeps=500, threshold=0.5, max_iterations=400),
+    dict(L=12, T=2.0, n_walkers=256, seed=0, sweeps=2000, threshold=0.5, max_iterations=300),
+)

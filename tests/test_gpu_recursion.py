@@ -1,0 +1,69 @@
+"""Faster weight recursions on the GPU path vs the oracle: the library's
+accumulated and extrapolating recursions give bit-identical weights, and hence
+bit-identical chains, iteration after iteration."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_07214_amd import REC_ACCUMULATED, REC_EXTRAPOLATE, MucaError, MucaJob
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("L,T,nw,flags", [
+    (4, 2.0, 16, REC_ACCUMULATED),
+    (4, 2.0, 16, REC_EXTRAPOLATE),
+    (4, 2.0, 16, REC_ACCUMULATED | REC_EXTRAPOLATE),
+    (5, 1.0, 32, REC_ACCUMULATED | REC_EXTRAPOLATE),
+    (6, 1.4182, 64, REC_ACCUMULATED | REC_EXTRAPOLATE),
+])
+def test_recursion_variants_match_oracle(L, T, nw, flags):
+    say(f"[recursion] L={L} T={T} walkers={nw} flags={flags}")
+    job = MucaJob(L, T, nw, seed=31, max_delta=1)
+    job.set_recursion(flags)
+    o = oracle.OracleJob(L, T, nw, 31)
+    o.set_recursion(flags)
+    for it in range(12):
+        job.sweep(300)
+        h = job.reduce_hist()
+        o.sweep(300)
+        ho = o.take_hist()
+        assert np.array_equal(h, ho), f"histogram differs at iteration {it}"
+        f = job.update_weights(h)
+        fo = o.update_weights(ho)
+        assert f == fo
+        assert job.lnW.tobytes() == o.lnW.tobytes(), f"weights differ at iteration {it}"
+    spins, state = job.read_state()
+    assert np.array_equal(spins, o.spins) and np.array_equal(state, o.state)
+    job.free()
+
+
+def test_switching_recursion_restarts_its_statistics():
+    L, T, nw = 4, 2.0, 16
+    say("[recursion] switch")
+    job = MucaJob(L, T, nw, seed=5, max_delta=1)
+    o = oracle.OracleJob(L, T, nw, 5)
+    for flags in (0, REC_ACCUMULATED, REC_ACCUMULATED | REC_EXTRAPOLATE, REC_ACCUMULATED):
+        job.set_recursion(flags)
+        o.set_recursion(flags)
+        for it in range(3):
+            job.sweep(200)
+            o.sweep(200)
+            job.update_weights(job.reduce_hist())
+            o.update_weights(o.take_hist())
+        assert job.lnW.tobytes() == o.lnW.tobytes()
+    job.free()
+
+
+def test_unknown_recursion_flags_are_rejected():
+    job = MucaJob(3, 2.0, 4, seed=0, max_delta=1)
+    with pytest.raises(MucaError):
+        job.set_recursion(4)
+    job.free()
