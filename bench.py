@@ -134,9 +134,9 @@ def served_leg():
     sp = workloads.SERVED
     reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"])
     cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"])
-    fast = dataclasses.replace(cfg, recursion=REC_EXTRAPOLATE)
+    fast = dataclasses.replace(cfg, recursion=REC_ACC_EXT)
     out = {"spec": {k: v for k, v in sp.items()}}
-    for mode, fn, c in (("served", serve, cfg), ("plain", serve_plain, cfg), ("served_extrapolating", serve, fast)):
+    for mode, fn, c in (("served", serve, cfg), ("plain", serve_plain, cfg), ("served_fast_recursion", serve, fast)):
         r = fn(reqs, c)
         out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "makespan_s", "jobs_per_s", "attempts_per_s",
                                        "latency_p50_s", "latency_p99_s", "iterations_p50", "queue_depth_max")}

@@ -148,7 +148,8 @@ int muca_update_weights(muca_job *job, const int64_t *hist, double *lnW_out, dou
  *     take the mean of every iteration's estimate d(E) + ln H(E) - ln H(E+1),
  *     weighted by its inverse Poisson variance H(E)H(E+1)/(H(E)+H(E+1)); a
  *     pair with one visited bin takes the plain step; lnW(0) is kept and the
- *     rest rebuilt from the differences.
+ *     rest rebuilt from the differences.  The accumulated statistics restart
+ *     whenever an iteration reaches a bin no earlier iteration did.
  *   MUCA_REC_EXTRAPOLATE: bins outside the range visited in any iteration so
  *     far continue the mean slope of the last min(8, width) differences inside
  *     it, at each end.

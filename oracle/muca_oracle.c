@@ -384,6 +384,10 @@ double orc_update_weights(int V, const int64_t *hist, double *lnW)
 /*   plain step (the empty side counts as one entry); a pair with none keeps  */
 /*   d.  The weights are rebuilt from d upwards from bin 0, whose value is    */
 /*   kept.  With K starting at 0 the first iteration is the plain recursion.  */
+/*   K restarts at 0 whenever an iteration reaches a bin no earlier one did: */
+/*   the estimates gathered before were sampled while part of the range was  */
+/*   out of reach, and averaging them in freezes their bias (measured: at    */
+/*   T < 1.1 it multiplied the iterations to flatness several times).        */
 /* flags & 2 (extrapolate): bins outside the range [lo, hi] of bins visited  */
 /*   in any iteration so far continue the slope of lnW over the last         */
 /*   k = min(8, hi - lo) bins inside the range, at each end.                  */
@@ -394,13 +398,23 @@ double orc_update_weights_ex(int V, const int64_t *hist, double *lnW, unsigned f
                              uint8_t *seen)
 {
     int64_t total = 0, least = hist[0];
+    int any_seen = 0, reached_new = 0;
+    for (int E = 0; E <= V; E++)
+        if (seen[E])
+            any_seen = 1;
     for (int E = 0; E <= V; E++) {
         total += hist[E];
         if (hist[E] < least)
             least = hist[E];
-        if (hist[E] > 0)
+        if (hist[E] > 0) {
+            if (!seen[E])
+                reached_new = 1;
             seen[E] = 1;
+        }
     }
+    if ((flags & 1u) && any_seen && reached_new)
+        for (int E = 0; E < V; E++)
+            kacc[E] = 0.0;
     if (flags & 1u) {
         double *d = (double *)malloc(sizeof(double) * (size_t)(V > 0 ? V : 1));
         for (int E = 0; E < V; E++)

@@ -479,6 +479,7 @@ namespace {
 // each iteration's estimate of the flat-histogram difference enters with its
 // inverse Poisson variance k = H(E) H(E+1) / (H(E) + H(E+1)); a pair with one
 // visited bin takes the plain step; the weights are rebuilt upwards from bin 0.
+// The caller restarts the sums when an iteration reaches a new bin.
 void accumulated_step(int V, const int64_t *hist, double *lnW, double *kacc)
 {
     std::vector<double> d(std::max(V, 1));
@@ -527,11 +528,20 @@ int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, doubl
         if (hist[E] < 0) return MUCA_E_INVAL;
     if (int rc = use_device(j)) return rc;
     int64_t sum = 0, least = hist[0];
+    bool any_seen = false, reached_new = false;
+    for (int E = 0; E <= V; ++E) any_seen = any_seen || j->seen[E];
     for (int E = 0; E <= V; ++E) {
         sum += hist[E];
         least = std::min(least, hist[E]);
-        if (hist[E] > 0) j->seen[E] = 1;
+        if (hist[E] > 0) {
+            reached_new = reached_new || !j->seen[E];
+            j->seen[E] = 1;
+        }
     }
+    // estimates sampled before the range grew are biased by the part that was
+    // out of reach: the accumulated statistics restart
+    if ((j->rec_flags & MUCA_REC_ACCUMULATED) && any_seen && reached_new)
+        std::fill(j->kacc.begin(), j->kacc.end(), 0.0);
     if (j->rec_flags & MUCA_REC_ACCUMULATED) {
         accumulated_step(V, hist, j->lnW.data(), j->kacc.data());
     } else {

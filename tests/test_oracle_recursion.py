@@ -177,3 +177,21 @@ def test_accumulated_is_the_inverse_variance_mean_of_the_estimates():
         den += w
         job.update_weights(h)
         assert np.allclose(np.diff(job.lnW), num / den, rtol=0, atol=1e-10)
+
+
+def test_accumulated_statistics_restart_when_the_range_grows():
+    # after an iteration that reaches a new bin, the next step is the plain
+    # one again (the earlier estimates carry the bias of the missing range)
+    h1 = np.array([0, 0, 30, 40, 50, 0, 0, 0, 0], dtype=np.int64)
+    h2 = np.array([0, 0, 60, 10, 20, 5, 0, 0, 0], dtype=np.int64)
+    a, p = fresh(2, flags=ACC), fresh(2, flags=0)
+    for h in (h1, h2):
+        a.update_weights(h)
+        p.update_weights(h)
+    assert np.allclose(np.diff(a.lnW)[1:6], np.diff(p.lnW)[1:6], rtol=0, atol=1e-12)
+    # without growth the same second histogram is averaged with the first
+    h2b = np.array([0, 0, 60, 10, 20, 0, 0, 0, 0], dtype=np.int64)
+    b = fresh(2, flags=ACC)
+    b.update_weights(h1)
+    b.update_weights(h2b)
+    assert not np.allclose(np.diff(b.lnW)[2:4], np.diff(p.lnW)[2:4])
