@@ -137,8 +137,9 @@ def _wait_until(t0: float, t: float):
         time.sleep(dt)
 
 
-def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False) -> dict:
-    """Continuous batching over the request stream (real time)."""
+def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False, progress=None) -> dict:
+    """Continuous batching over the request stream (real time).  progress, if
+    given, is called with the finished job records as jobs finish."""
     import torch
 
     t0 = time.perf_counter()
@@ -189,6 +190,8 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
         if done:
             batch.free()
             batch = None
+            if progress is not None:
+                progress([a.rec for a in done])
             for a in done:
                 walkers -= a.rec.req.n_walkers
                 nbytes -= footprint(a.rec.req)
