@@ -223,7 +223,7 @@ def cpu_baseline(w, deltas):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the walker-sharded multi-GPU path is a design, not code",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

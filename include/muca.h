@@ -50,7 +50,7 @@ extern "C" {
 
 #define MUCA_OK 0
 #define MUCA_E_INVAL (-1)       /* bad argument: L, T, n_walkers, null pointer, range */
-#define MUCA_E_UNSUPPORTED (-2) /* valid request this build does not implement */
+#define MUCA_E_UNSUPPORTED (-2) /* valid request the library does not implement */
 #define MUCA_E_SIZE (-3)        /* buffer too small / too large for a fixed limit */
 #define MUCA_E_STATE (-4)       /* call out of order (e.g. reweight with no recorded data) */
 #define MUCA_E_OVERFLOW (-5)    /* a counter would overflow (n_sweeps per call) */
