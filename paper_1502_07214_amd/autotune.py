@@ -12,7 +12,6 @@ import json
 import os
 from typing import Optional, Sequence
 
-import numpy as np
 
 from .muca import MucaBatch, MucaError, MucaJob
 

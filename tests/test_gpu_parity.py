@@ -1,7 +1,6 @@
 """GPU path vs oracle, through the C ABI: trajectories (lattices, E_J, E_Delta,
 M, sweep counters), per-iteration histograms and weights bit for bit, per-bin
 production sums bit for bit, reweighted observables to 1e-12 relative."""
-import math
 import sys
 
 import numpy as np

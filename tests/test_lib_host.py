@@ -3,7 +3,6 @@ every function include/muca.h declares; its threshold tables and visiting order
 are bitwise identical to the oracle's (independent code, same host libm); its
 argument checks return the documented error codes."""
 import ctypes
-import math
 import os
 import re
 
