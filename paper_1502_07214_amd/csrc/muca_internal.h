@@ -13,7 +13,7 @@ constexpr int kMaxClasses = 3;       // colours of the visiting order
 constexpr int kLdsFixed = 384;       // B'[32] doubles + scan scratch at the start of LDS
 constexpr int kMaxSweepsPerLaunch = 1 << 26;
 constexpr int kMaxCachedPasses = 4;  // passes per sweep whose neighbour positions stay in registers
-constexpr int kRPad = 4;             // threshold-table entries padded below E = 0 and above E = V
+constexpr int kRPad = 8;             // threshold-table entries padded below E = 0 and above E = V (>= sites per lane - 1)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -171,14 +171,15 @@ struct Walker {
         // chunk then holds the exact chain from the exact E_Delta before it.
         // Chunk 0 always starts right, so after k exchanges the first k chunks
         // do, and at most WPW + 1 exchanges happen (the first one after round 0).
+        static_assert(NS - 1 <= kRPad, "guesses of a lane's later sites must stay inside the padded table");
         int ddv[NS], ridx[NS];
-        bool acc0[NS];
+        unsigned acc0 = 0u;  // bit k: the decision of site k where d == 0
         uint64_t SENS[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             ddv[k] = valid[k] ? dd[k] : 0;   // E_Delta step if accepted
             ridx[k] = dd[k] > 0 ? 1 : 0;     // 0: R_-, 1: R_+
-            acc0[k] = valid[k] && u[k] < bp[k];  // the decision where d == 0
+            acc0 |= (valid[k] && u[k] < bp[k] ? 1u : 0u) << k;
             SENS[k] = __ballot(ddv[k] != 0);
         }
         bool c[NS];      // this lane's decisions of the last round
@@ -216,7 +217,7 @@ struct Walker {
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int k = 4 * q + t;
-                    const bool a = ddv[k] != 0 ? c[k] : acc0[k];
+                    const bool a = ddv[k] != 0 ? c[k] : ((acc0 >> k) & 1u) != 0u;
                     nw |= ((unsigned)(a ? snew[k] : sold[k]) & 0xffu) << (8 * t);
                 }
                 if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
@@ -240,13 +241,13 @@ struct Walker {
         scan();
         if (WPW > 1) exchange(off);
         int base = ED + off[wave];
-        int Eg[NS];
+        // eb: the guess at the lane's first site; site k is guessed at eb + ex[k].
+        // One clamp per lane keeps the table reads in bounds (the padding covers
+        // ex); at the fixed point every guess is a true E_Delta and untouched.
+        int eb = base + laneOff;
         uint64_t moved = 0;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            Eg[k] = base + laneOff + ex[k];
-            moved |= __ballot(Eg[k] != ED) & SENS[k];
-        }
+        for (int k = 0; k < NS; ++k) moved |= __ballot(eb + ex[k] != ED) & SENS[k];
         // round 0 decided at E_Delta itself: done unless a guess moved
         bool again = moved != 0;
         unsigned nround = 1;
@@ -257,8 +258,9 @@ struct Walker {
             int inner = 0;
             while (again) {
                 double r[NS];
+                const int ce = clamp0(eb, V);
 #pragma unroll
-                for (int k = 0; k < NS; ++k) r[k] = R[2 * clamp0(Eg[k], V) + ridx[k]];
+                for (int k = 0; k < NS; ++k) r[k] = R[2 * (ce + ex[k]) + ridx[k]];
                 uint64_t diff = 0;
 #pragma unroll
                 for (int k = 0; k < NS; ++k) {
@@ -270,8 +272,7 @@ struct Walker {
                 ++nround;
                 if (diff == 0) break;
                 scan();
-#pragma unroll
-                for (int k = 0; k < NS; ++k) Eg[k] = base + laneOff + ex[k];
+                eb = base + laneOff;
                 if (++inner > cap) {
                     if (lane == 0) atomicOr(err, 1);
                     break;
@@ -293,14 +294,13 @@ struct Walker {
 #pragma unroll
             for (int v = 0; v < 4; ++v) off[v] = no[v];
             base += shift;
-#pragma unroll
-            for (int k = 0; k < NS; ++k) Eg[k] += shift;
+            eb += shift;
             again = shift != 0;
         }
         const int total = wsum;
         bool acc[NS];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] = ddv[k] != 0 ? c[k] : acc0[k];
+        for (int k = 0; k < NS; ++k) acc[k] = ddv[k] != 0 ? c[k] : ((acc0 >> k) & 1u) != 0u;
         rounds = nround;
         // ---- apply the accepted moves ----
         write_spins();
