@@ -42,7 +42,7 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # workload: FETCH_SIZE + WRITE_SIZE from rocprofv3, each scaled by the same
 # counter's reading on a plain 1 GiB copy (profiles/sweep_kernel_l12_t2_w256_pmc.txt).
 TRAFFIC_KERNEL = "muca_sweep_kernel<4, 1, false, true, 2>"
-TRAFFIC_BYTES_PER_LAUNCH = 1889996
+TRAFFIC_BYTES_PER_LAUNCH = 1887266
 # weight recursions of the convergence legs (flags of muca_set_recursion)
 REC_EXTRAPOLATE, REC_ACC_EXT = 2, 3
 
@@ -279,7 +279,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
                      "traffic": TRAFFIC_BYTES_PER_LAUNCH if shape == {"waves_per_walker": 4, "blocks_per_lane": 1,
-                                                                      "lds_tables": 1, "lds_bytes": 36832} else None,
+                                                                      "lds_tables": 1, "lds_bytes": 36960} else None,
                      "kernel": "muca_sweep_kernel", "slots_per_attempt": ALGO_SLOTS_PER_ATTEMPT},
     }
     if not args.no_extra:
