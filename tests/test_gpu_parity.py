@@ -235,3 +235,30 @@ def test_walker_split_equals_whole():
         parts.append(o.take_hist())
     assert np.array_equal(h, sum(parts))
     job.free()
+
+
+@pytest.mark.parametrize("wpw", [1, 2, 4])
+def test_jagged_weights_many_rounds(wpw):
+    """Weights with strong bin-to-bin noise make decisions flip with every
+    change of the guessed E_Delta: long cascades, many fixed-point rounds and,
+    with several waves per walker, several exchanges per pass.  The chain must
+    still be the sequential one."""
+    L, T, nw, seed = 10, 1.5, 9, 41
+    V = L ** 3
+    rng = np.random.default_rng(5)
+    lnW = -(2.8 / T) * np.arange(V + 1) + rng.normal(0.0, 1.5, size=V + 1)
+    say(f"[parity] jagged weights L={L} walkers={nw} wpw={wpw}")
+    job = MucaJob(L, T, nw, seed=seed, lnW=lnW, max_delta=1)
+    job.set_launch(wpw, 1, -1)
+    job.set_stats(True)
+    o = oracle.OracleJob(L, T, nw, seed, lnW=lnW)
+    job.sweep(40)
+    o.sweep(40)
+    st = job.read_stats()
+    say(f"[parity] jagged weights: {st['rounds'] / st['passes']:.1f} rounds per pass (summed over waves)")
+    assert np.array_equal(job.reduce_hist(), o.take_hist())
+    spins, state = job.read_state()
+    assert np.array_equal(spins, o.spins) and np.array_equal(state, o.state)
+    # the case is a stress case: far more rounds than the 2 of smooth weights
+    assert st["rounds"] / st["passes"] > 4 * wpw, st
+    job.free()
