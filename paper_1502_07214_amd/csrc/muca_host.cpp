@@ -807,6 +807,7 @@ struct muca_batch {
     int wpw, bpl, blocks;
     int max_vp;
     size_t total_walkers;
+    size_t tab_bytes;  // LDS reserved for staged tables (0: every job reads them through the caches)
 };
 
 namespace {
@@ -829,6 +830,8 @@ int build_tiles(muca_batch *b, int wpw, std::vector<int2> &tiles)
         for (int w = 0; w < b->jobs[jx]->g.n_walkers; w += wpb) tiles.push_back(make_int2(jx, w));
     return (int)tiles.size();
 }
+
+size_t job_tab_bytes(const muca_job *j);
 
 int upload_batch(muca_batch *b)
 {
@@ -855,6 +858,7 @@ int upload_batch(muca_batch *b)
         for (int c = 0; c <= kMaxClasses; ++c) J.cls[c] = g.cls[c];
         J.k0 = j->k0;
         J.k1 = j->k1;
+        J.lds_tables = b->tab_bytes > 0 && job_tab_bytes(j) <= b->tab_bytes ? 1 : 0;
     }
     const size_t off_tiles = align_up(bj.size() * sizeof(BatchJob), 256);
     HIP_TRY(hipMemcpyAsync(b->dev, bj.data(), bj.size() * sizeof(BatchJob), hipMemcpyHostToDevice, b->stream));
@@ -865,6 +869,28 @@ int upload_batch(muca_batch *b)
 }
 
 size_t batch_lds(const muca_batch *b, int wpw) { return kLdsFixed + align_up((size_t)(4 / wpw) * b->max_vp, 16); }
+
+// LDS a job's thresholds and neighbour table take when staged.
+size_t job_tab_bytes(const muca_job *j)
+{
+    return align_up(16 * ((size_t)j->g.V + 1 + 2 * kRPad), 16) + align_up((size_t)12 * j->g.Vp, 16);
+}
+
+// Per-block LDS up to which a batch stages tables: enough for the thresholds
+// of served-size jobs while four blocks still fit on a CU.
+constexpr size_t kBatchLdsBudget = 40 * 1024;
+
+// The largest staged-table size that keeps the block within the budget.
+size_t choose_tab_bytes(const muca_batch *b, int wpw)
+{
+    const size_t base = batch_lds(b, wpw);
+    size_t best = 0;
+    for (const muca_job *j : b->jobs) {
+        const size_t t = job_tab_bytes(j);
+        if (base + t <= kBatchLdsBudget) best = std::max(best, t);
+    }
+    return best;
+}
 
 }  // namespace
 
@@ -921,6 +947,7 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
         delete b;
         return rc;
     }
+    b->tab_bytes = choose_tab_bytes(b, b->wpw);
     if (int rc = upload_batch(b)) {
         delete b;
         return rc;
@@ -938,7 +965,10 @@ int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t block
     b->wpw = wpw;
     b->bpl = bpl;
     b->blocks = blocks > 0 ? blocks : 0;
-    if (old != wpw) return upload_batch(b);
+    if (old != wpw) {
+        b->tab_bytes = choose_tab_bytes(b, wpw);
+        return upload_batch(b);
+    }
     return MUCA_OK;
 }
 
@@ -956,13 +986,14 @@ int muca_batch_sweep(muca_batch *b, int64_t n_sweeps, uint32_t flags)
     a.n_tiles = b->n_tiles;
     a.counter = reinterpret_cast<unsigned *>(b->dev + off_counter);
     a.lds_off_lat = kLdsFixed;
+    a.lds_off_tab = (int)batch_lds(b, b->wpw);
     const bool record = (flags & MUCA_RECORD) != 0;
     int64_t left = n_sweeps;
     while (left > 0) {
         const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
         a.n_sweeps = chunk;
         HIP_TRY(launch_zero(b->dev + off_counter, 16, b->stream));
-        HIP_TRY(launch_batch(a, b->wpw, b->bpl, record, batch_lds(b, b->wpw), b->blocks, b->stream));
+        HIP_TRY(launch_batch(a, b->wpw, b->bpl, record, batch_lds(b, b->wpw) + b->tab_bytes, b->blocks, b->stream));
         left -= chunk;
     }
     if (record)

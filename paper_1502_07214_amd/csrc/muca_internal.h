@@ -89,6 +89,7 @@ struct BatchJob {
     int V, Vp, n_walkers, n_classes;
     int cls[kMaxClasses + 1];
     uint32_t k0, k1;
+    int lds_tables;          // 1: thresholds and neighbour table staged in LDS for this job's tiles
 };
 
 struct BatchArgs {
@@ -98,6 +99,7 @@ struct BatchArgs {
     unsigned *counter;       // work counter, zero at launch
     int n_sweeps;
     int lds_off_lat;         // LDS offset of the lattice slots (sized for the largest job)
+    int lds_off_tab;         // LDS offset of the staged tables (jobs with lds_tables)
 };
 
 // Launchers (muca_kernels.hip).  Return the hipError_t of the launch.

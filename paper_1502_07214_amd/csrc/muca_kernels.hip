@@ -414,14 +414,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     }
     __syncthreads();
 
+    // diagnostics, summed in registers and added to the counters once at the end
+    unsigned long long st_passes = 0, st_rounds = 0, st_accepted = 0;
+    const bool want_stats = a.stats != nullptr;
     auto stats_after_pass = [&]() {
-        if (a.stats != nullptr) {
-            const unsigned n = wave_total(wave_incl_sum(wk.accepted));
-            if (live && lane == 0) {
-                atomicAdd(&a.stats[2], (unsigned long long)n);
-                atomicAdd(&a.stats[1], (unsigned long long)wk.rounds);
-                if (lg == 0) atomicAdd(&a.stats[0], 1ull);
-            }
+        if (want_stats) {
+            st_accepted += wave_total(wave_incl_sum(wk.accepted));
+            st_rounds += wk.rounds;
+            st_passes += 1;
         }
     };
 
@@ -505,6 +505,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
         }
     }
 
+    if (want_stats && live && lane == 0) {
+        atomicAdd(&a.stats[2], st_accepted);
+        atomicAdd(&a.stats[1], st_rounds);
+        if (lg == 0) atomicAdd(&a.stats[0], st_passes);
+    }
     // ---- write back ----
     unsigned ej = wave_total(wave_incl_sum(wk.myEJ));
     unsigned m = wave_total(wave_incl_sum(wk.myM));
@@ -547,8 +552,9 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
 // Batched persistent sweep: walkers of many jobs (different L, T, weights) in
 // one launch.  Blocks pull tiles (4 / WPW walkers of one job) from a work
 // counter until the list is exhausted; the host orders the list heaviest
-// first.  Thresholds and neighbour tables are read through the caches, spins
-// are staged in LDS, histograms go straight to each job's buffer.  Each walker
+// first.  Spins are staged in LDS; thresholds and neighbour tables too for
+// the jobs whose tables fit the batch's LDS budget (else they are read through
+// the caches); histograms go straight to each job's buffer.  Each walker
 // runs exactly the chain it runs in its own job's launch.
 // ---------------------------------------------------------------------------
 template <int WPW, int BPL, bool RECORD>
@@ -588,9 +594,15 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
         a.lds_hist = 0;
         a.lds_off_hist = kLdsFixed;
         a.lds_off_lat = b.lds_off_lat;
-        a.lds_off_r = 0;
-        a.lds_off_nb = 0;
-        sweep_tile<WPW, BPL, RECORD, false, 0>(a, tile.y, smem);
+        if (J.lds_tables) {
+            a.lds_off_r = b.lds_off_tab;
+            a.lds_off_nb = b.lds_off_tab + ((16 * (J.V + 1 + 2 * kRPad) + 15) & ~15);
+            sweep_tile<WPW, BPL, RECORD, true, 0>(a, tile.y, smem);
+        } else {
+            a.lds_off_r = 0;
+            a.lds_off_nb = 0;
+            sweep_tile<WPW, BPL, RECORD, false, 0>(a, tile.y, smem);
+        }
     }
 }
 
