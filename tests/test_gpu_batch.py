@@ -81,3 +81,29 @@ def test_batch_rejects_bad_input():
         batch.sweep(-1)
     batch.free()
     j.free()
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (4, 1)])
+def test_batch_mixes_staged_and_cached_tables(shape):
+    """A large lattice fills the batch's LDS with spins, so only the smallest
+    jobs get their tables staged in LDS; the others read them through the
+    caches in the same launch."""
+    mix = [(20, 1.5, 2, 21), (4, 1.0, 9, 14), (5, 2.0, 6, 12), (8, 0.9, 3, 11)]
+    print(f"[batch] staged + cached tables {mix} shape {shape}", flush=True)
+    a = [MucaJob(L, T, nw, seed=s, max_delta=1) for (L, T, nw, s) in mix]
+    b = [MucaJob(L, T, nw, seed=s, max_delta=1) for (L, T, nw, s) in mix]
+    batch = MucaBatch(a)
+    batch.set_launch(*shape)
+    ha = iterate(a, batch.sweep, 2, 20)
+    hb = iterate(b, lambda n: [j.sweep(n) for j in b], 2, 20)
+    for it in range(2):
+        for x, y in zip(ha[it], hb[it]):
+            assert np.array_equal(x, y)
+    for ja, jb in zip(a, b):
+        sa, sta = ja.read_state()
+        sb, stb = jb.read_state()
+        assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+        assert ja.lnW.tobytes() == jb.lnW.tobytes()
+    batch.free()
+    for j in a + b:
+        j.free()
