@@ -414,14 +414,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     }
     __syncthreads();
 
-    // diagnostics, summed in registers and added to the counters once at the end
-    unsigned long long st_passes = 0, st_rounds = 0, st_accepted = 0;
-    const bool want_stats = a.stats != nullptr;
+    // diagnostics (off unless requested: they cost three atomics per wave and pass)
     auto stats_after_pass = [&]() {
-        if (want_stats) {
-            st_accepted += wave_total(wave_incl_sum(wk.accepted));
-            st_rounds += wk.rounds;
-            st_passes += 1;
+        if (a.stats != nullptr) {
+            const unsigned n = wave_total(wave_incl_sum(wk.accepted));
+            if (live && lane == 0) {
+                atomicAdd(&a.stats[2], (unsigned long long)n);
+                atomicAdd(&a.stats[1], (unsigned long long)wk.rounds);
+                if (lg == 0) atomicAdd(&a.stats[0], 1ull);
+            }
         }
     };
 
@@ -505,11 +506,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
         }
     }
 
-    if (want_stats && live && lane == 0) {
-        atomicAdd(&a.stats[2], st_accepted);
-        atomicAdd(&a.stats[1], st_rounds);
-        if (lg == 0) atomicAdd(&a.stats[0], st_passes);
-    }
     // ---- write back ----
     unsigned ej = wave_total(wave_incl_sum(wk.myEJ));
     unsigned m = wave_total(wave_incl_sum(wk.myM));
