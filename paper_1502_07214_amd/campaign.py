@@ -31,14 +31,17 @@ POINTS = (
     (8, 2.0, 512, 1000, 600, 8, 5000),
     (12, 2.0, 512, 2000, 600, 8, 10000),
     (16, 2.0, 1024, 4000, 600, 8, 10000),
+    (16, 1.0, 1024, 4000, 1500, 8, 10000),
+    (20, 2.0, 1024, 4000, 800, 8, 10000),
 )
 FIRST_ORDER_T = 1.4182  # below the tricritical temperature the transition is first order
 
 
-def converge(job: MucaJob, sweeps: int, cap: int, threshold: float = 0.5) -> dict:
+def converge(job: MucaJob, sweeps: int, cap: int, threshold: float = 0.5, log=None) -> dict:
     """Iterate until the merged histogram is flat (min/mean > threshold on
     [0, V]) or the cap is reached; the weights are updated after every
-    iteration that is not yet flat."""
+    iteration that is not yet flat.  log(iteration, flatness) is called every
+    50 iterations."""
     V = job.V
     f = 0.0
     it = 0
@@ -47,6 +50,8 @@ def converge(job: MucaJob, sweeps: int, cap: int, threshold: float = 0.5) -> dic
         h = job.reduce_hist(reset=True)
         it += 1
         f = muca_flatness(h, 0, V)
+        if log is not None and it % 50 == 0:
+            log(it, f)
         if f > threshold:
             break
         job.update_weights(h)
@@ -59,14 +64,14 @@ def _bracket(grid: np.ndarray, values: np.ndarray):
 
 
 def run_point(L: int, T: float, walkers: int, sweeps: int, cap: int, n_blocks: int, block_sweeps: int,
-              seed: int = 0, grid=None) -> dict:
+              seed: int = 0, grid=None, log=None) -> dict:
     t0 = time.perf_counter()
     dm = delta_mid(T)
     grid = np.linspace(dm - 1.0, dm + 0.5, 301) if grid is None else np.asarray(grid, dtype=np.float64)
     job = MucaJob(L, T, walkers, seed=seed, lnW=tilted_weights(L, T), max_delta=len(grid))
     job.set_recursion(REC_ACCUMULATED | REC_EXTRAPOLATE)
     out = {"L": L, "T": T, "walkers": walkers, "sweeps_per_iteration": sweeps}
-    out.update(converge(job, sweeps, cap))
+    out.update(converge(job, sweeps, cap, log=log))
     blocks, total = analysis.production_blocks(job, n_blocks, block_sweeps)
     out["production_sweeps"] = n_blocks * block_sweeps
     cs = job.reweight_sums(total, grid)[:, _C]
@@ -103,7 +108,8 @@ def main(argv):
         pts = [p for p in POINTS if (p[0], p[1]) in want]
     for p in pts:
         print(f"[campaign] L={p[0]} T={p[1]}", file=sys.stderr, flush=True)
-        print(json.dumps(run_point(*p)), flush=True)
+        log = lambda it, f: print(f"[campaign]   iteration {it}: flatness {f:.3f}", file=sys.stderr, flush=True)
+        print(json.dumps(run_point(*p, log=log)), flush=True)
 
 
 if __name__ == "__main__":
