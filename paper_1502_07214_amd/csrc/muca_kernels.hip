@@ -250,6 +250,11 @@ struct Walker {
         for (int k = 0; k < NS; ++k) moved |= __ballot(eb + ex[k] != ED) & SENS[k];
         // round 0 decided at E_Delta itself: done unless a guess moved
         bool again = moved != 0;
+        // the pass's spins in LDS lag its decisions (uniform): with several
+        // waves per walker they are written before an exchange whenever they
+        // changed, so the exchange that ends the pass also orders them before
+        // the next pass reads them
+        bool dirty = true;
         unsigned nround = 1;
         int outer = 0;
         const int cap = 64 * NS + 2;
@@ -271,6 +276,7 @@ struct Walker {
                 }
                 ++nround;
                 if (diff == 0) break;
+                dirty = true;
                 scan();
                 eb = base + laneOff;
                 if (++inner > cap) {
@@ -281,6 +287,10 @@ struct Walker {
             if (WPW == 1) {
                 wsum = (int)wave_total(incl);
                 break;
+            }
+            if (dirty) {
+                write_spins();
+                dirty = false;
             }
             int no[4];
             exchange(no);
@@ -303,7 +313,7 @@ struct Walker {
         for (int k = 0; k < NS; ++k) acc[k] = ddv[k] != 0 ? c[k] : ((acc0 >> k) & 1u) != 0u;
         rounds = nround;
         // ---- apply the accepted moves ----
-        write_spins();
+        if (dirty) write_spins();
         unsigned nacc = 0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -432,12 +442,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
             for (int cp = 0; cp < (NCP > 0 ? NCP : 1); ++cp) {
                 wk.pass(a.pass_p0[cp], a.pass_p1[cp], a.pass_jbase[cp], sweep, nbc[cp], a.err);
                 stats_after_pass();
-                if ((a.pass_sync >> cp) & 1u) {
-                    if (WPW > 1)
-                        __syncthreads();
-                    else
-                        wave_sync_lds();
-                }
+                // with several waves per walker the pass ended on a barrier
+                if (WPW == 1 && ((a.pass_sync >> cp) & 1u)) wave_sync_lds();
             }
         } else {
             for (int c = 0; c < a.n_classes; ++c) {
@@ -456,10 +462,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
                     wk.pass(P0, P1, jbase, sweep, nq, a.err);
                     stats_after_pass();
                 }
-                if (WPW > 1)
-                    __syncthreads();
-                else
-                    wave_sync_lds();
+                if (WPW == 1) wave_sync_lds();
             }
         }
         sweep += 1u;
