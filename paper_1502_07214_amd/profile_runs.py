@@ -2,12 +2,16 @@
 
     python -m paper_1502_07214_amd.profile_runs copy    # plain device copy of 1 GiB, 3 times
     python -m paper_1502_07214_amd.profile_runs sweep   # the benchmark's sweep launches (L=12, 256 walkers)
+    python -m paper_1502_07214_amd.profile_runs saturation  # L=8, 65 536 walkers, 10 + 100 sweeps
+    python -m paper_1502_07214_amd.profile_runs batched     # 19 mixed jobs: 10 batched launches of 1000 sweeps
 
 `copy` calibrates the FETCH_SIZE / WRITE_SIZE counters: each copy moves exactly
 2^30 bytes in and 2^30 bytes out of HBM, so counter / 2^30 is the factor that
 turns the counters of other kernels into bytes.  `sweep` runs three
 iterations of the benchmark job (10^4 sweeps of 256 walkers at L = 12, T = 2,
-each followed by the histogram merge and weight update).
+each followed by the histogram merge and weight update).  `saturation` and
+`batched` are the saturation job and the batched workload of the benchmark
+(its batched mode only).
 """
 from __future__ import annotations
 
@@ -42,5 +46,38 @@ def sweep(iterations: int = 3):
     job.free()
 
 
+def saturation():
+    import torch
+
+    from . import MucaJob, workloads
+
+    s = workloads.SATURATION
+    job = MucaJob(s["L"], s["T"], s["n_walkers"], seed=s["seed"], max_delta=1)
+    job.sweep(10)
+    job.sweep(s["sweeps"])
+    torch.cuda.synchronize()
+    print(f"saturation: {s['n_walkers']} walkers at L={s['L']}, 10 + {s['sweeps']} sweeps", flush=True)
+    job.free()
+
+
+def batched():
+    import torch
+
+    from . import MucaBatch, MucaJob, workloads
+
+    specs = workloads.batched_jobs()
+    jobs = [MucaJob(L, T, n, seed=sd, max_delta=1) for (L, T, n, sd) in specs]
+    batch = MucaBatch(jobs)
+    for it in range(workloads.BATCHED["iterations"]):
+        batch.sweep(workloads.BATCHED["sweeps"])
+        for j in jobs:
+            j.update_weights(j.reduce_hist())
+        print(f"batched iteration {it} done", flush=True)
+    torch.cuda.synchronize()
+    batch.free()
+    for j in jobs:
+        j.free()
+
+
 if __name__ == "__main__":
-    {"copy": copy, "sweep": sweep}[sys.argv[1]]()
+    {"copy": copy, "sweep": sweep, "saturation": saturation, "batched": batched}[sys.argv[1]]()
