@@ -251,11 +251,22 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
                       muca_batch **out);
 
 /* Launch shape of the batched kernel (results do not depend on it):
- * waves_per_walker in {1, 2, 4}, blocks_per_lane in {1, 2}; blocks <= 0 fills
- * the device (occupancy query).  MUCA_E_SIZE if the lattice slots of the
- * largest job do not fit in LDS. */
+ * waves_per_walker in {0, 1, 2, 4}, blocks_per_lane in {1, 2}; blocks <= 0
+ * fills the device (occupancy query).  The default is one wave per walker for
+ * every job.  waves_per_walker 0 picks per job: four waves per walker for the
+ * jobs whose walkers would otherwise set the length of the launch (large
+ * lattices, few waves in the batch), one for the rest; it pays while the
+ * weights are smooth.  MUCA_E_SIZE if the lattice slots of the largest tile
+ * do not fit in LDS. */
 int muca_batch_set_launch(muca_batch *batch, int32_t waves_per_walker, int32_t blocks_per_lane,
                           int32_t blocks);
+
+/* The launch shape in use: the waves per walker of each job's tiles
+ * (waves_per_walker[k] for the k-th job passed to muca_batch_create, so an
+ * array of n_jobs), the Philox blocks per lane and the LDS bytes per block.
+ * Any pointer may be NULL.  MUCA_E_INVAL for a NULL batch. */
+int muca_batch_get_launch(const muca_batch *batch, int32_t *waves_per_walker, int32_t *blocks_per_lane,
+                          int32_t *lds_bytes);
 
 /* n_sweeps (0..MUCA_MAX_SWEEPS_PER_CALL) sweeps of every walker of every job in
  * the batch, in one persistent launch per at most 2^26 sweeps; flags as for

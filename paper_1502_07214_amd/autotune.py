@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 from .muca import MucaBatch, MucaError, MucaJob
 
 PLAIN_SHAPES = [(w, b, t) for w in (4, 2, 1) for b in (1, 2) for t in (1, 0)]
-BATCH_SHAPES = [(w, b) for w in (1, 2, 4) for b in (1, 2)]
+BATCH_SHAPES = [(w, b) for w in (0, 1, 2, 4) for b in (1, 2)]
 
 
 def _device_name() -> str:

@@ -804,8 +804,8 @@ struct muca_batch {
     unsigned char *dev;
     size_t bytes;
     int n_tiles;
-    int wpw, bpl, blocks;
-    int max_vp;
+    int wpw, bpl, blocks;  // wpw 0: each job's tiles use job_wpw
+    std::vector<int> job_wpw;
     size_t total_walkers;
     size_t tab_bytes;  // LDS reserved for staged tables (0: every job reads them through the caches)
 };
@@ -817,18 +817,63 @@ size_t batch_bytes(size_t n_jobs, size_t walkers)
     return align_up(n_jobs * sizeof(BatchJob), 256) + align_up(walkers * sizeof(int2), 256) + 256;
 }
 
+int tile_wpw(const muca_batch *b, int wpw, size_t k) { return wpw ? wpw : b->job_wpw[k]; }
+
 // Tiles of 4/wpw consecutive walkers of one job, jobs with the most work per
 // walker (largest V) first.
 int build_tiles(muca_batch *b, int wpw, std::vector<int2> &tiles)
 {
-    const int wpb = 4 / wpw;
     std::vector<int> idx(b->jobs.size());
     for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return b->jobs[x]->g.V > b->jobs[y]->g.V; });
     tiles.clear();
-    for (int jx : idx)
+    for (int jx : idx) {
+        const int wpb = 4 / tile_wpw(b, wpw, (size_t)jx);
         for (int w = 0; w < b->jobs[jx]->g.n_walkers; w += wpb) tiles.push_back(make_int2(jx, w));
+    }
     return (int)tiles.size();
+}
+
+// Waves per walker of each job in a launch that mixes them (an opt-in shape:
+// measured on the batched workloads, four-wave walkers of large lattices
+// shortened the first launches from a flat start about 2x but lengthened the
+// later ones, with steep weights, by 15-20 %, so one wave per walker for every
+// job is the default).  A walker at one
+// wave per walker is latency-bound at about 12 clocks per site; the whole
+// batch, spread over the device at the VALU issue limit, takes about 4 clocks
+// per site per SIMD.  A job whose walkers would outlast that share by the
+// first measure gets four waves per walker (a block each), provided its colour
+// classes fill 4 x 64 lanes of 4 sites, and provided every wave of the batch
+// still has a SIMD to itself: the waves of a walker meet at a barrier several
+// times per pass, so sharing their SIMDs with other waves costs them more than
+// it costs single-wave walkers (measured: slower once the weights are steep).
+// Jobs are promoted largest first.  A job whose four lattices do not fit in
+// LDS next to each other gets four waves (one lattice per block) regardless.
+void choose_job_wpw(muca_batch *b)
+{
+    double total = 0.0;
+    long waves = 0;
+    for (const muca_job *j : b->jobs) {
+        total += (double)j->g.V * (double)j->g.n_walkers;
+        waves += j->g.n_walkers;
+    }
+    const muca_job *j0 = b->jobs[0];
+    const long simds = 4L * (j0->n_cu > 0 ? j0->n_cu : 256);
+    b->job_wpw.assign(b->jobs.size(), 1);
+    std::vector<size_t> idx(b->jobs.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return b->jobs[x]->g.V > b->jobs[y]->g.V; });
+    for (size_t k : idx) {
+        const Layout &g = b->jobs[k]->g;
+        const bool fills = g.V / g.C >= 4 * 64 * 4;
+        const long extra = 3L * g.n_walkers;
+        if (fills && 3.0 * (double)g.V * (double)simds > total && waves + extra <= simds) {
+            b->job_wpw[k] = 4;
+            waves += extra;
+        }
+    }
+    for (size_t k = 0; k < b->jobs.size(); ++k)
+        if (kLdsFixed + align_up((size_t)4 * b->jobs[k]->g.Vp, 16) > (size_t)j0->max_lds) b->job_wpw[k] = 4;
 }
 
 size_t job_tab_bytes(const muca_job *j);
@@ -859,6 +904,7 @@ int upload_batch(muca_batch *b)
         J.k0 = j->k0;
         J.k1 = j->k1;
         J.lds_tables = b->tab_bytes > 0 && job_tab_bytes(j) <= b->tab_bytes ? 1 : 0;
+        J.wpw = tile_wpw(b, b->wpw, k);
     }
     const size_t off_tiles = align_up(bj.size() * sizeof(BatchJob), 256);
     HIP_TRY(hipMemcpyAsync(b->dev, bj.data(), bj.size() * sizeof(BatchJob), hipMemcpyHostToDevice, b->stream));
@@ -868,7 +914,14 @@ int upload_batch(muca_batch *b)
     return MUCA_OK;
 }
 
-size_t batch_lds(const muca_batch *b, int wpw) { return kLdsFixed + align_up((size_t)(4 / wpw) * b->max_vp, 16); }
+// LDS of a block: the fixed part and the lattice slots of the largest tile.
+size_t batch_lds(const muca_batch *b, int wpw)
+{
+    size_t lat = 0;
+    for (size_t k = 0; k < b->jobs.size(); ++k)
+        lat = std::max(lat, (size_t)(4 / tile_wpw(b, wpw, k)) * (size_t)b->jobs[k]->g.Vp);
+    return kLdsFixed + align_up(lat, 16);
+}
 
 // LDS a job's thresholds and neighbour table take when staged.
 size_t job_tab_bytes(const muca_job *j)
@@ -928,15 +981,14 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
     b->device = jobs[0]->device;
     b->dev = reinterpret_cast<unsigned char *>(dev_buffer);
     b->bytes = bytes;
-    b->max_vp = 0;
     b->total_walkers = 0;
     for (muca_job *j : b->jobs) {
-        b->max_vp = std::max(b->max_vp, j->g.Vp);
         b->total_walkers += (size_t)j->g.n_walkers;
     }
     b->wpw = 1;
     b->bpl = 1;
     b->blocks = 0;
+    choose_job_wpw(b);  // the shape of a per-job launch, if a caller asks for one
     const int max_lds = jobs[0]->max_lds;
     while (batch_lds(b, b->wpw) > (size_t)max_lds && b->wpw < 4) b->wpw *= 2;
     if (batch_lds(b, b->wpw) > (size_t)max_lds) {
@@ -958,7 +1010,7 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
 
 int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t blocks)
 {
-    if (!b || !(wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2)) return MUCA_E_INVAL;
+    if (!b || !(wpw == 0 || wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2)) return MUCA_E_INVAL;
     if (batch_lds(b, wpw) > (size_t)b->jobs[0]->max_lds) return MUCA_E_SIZE;
     if (int rc = use_device(b->jobs[0])) return rc;
     const int old = b->wpw;
@@ -969,6 +1021,17 @@ int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t block
         b->tab_bytes = choose_tab_bytes(b, wpw);
         return upload_batch(b);
     }
+    return MUCA_OK;
+}
+
+int muca_batch_get_launch(const muca_batch *b, int32_t *waves_per_walker, int32_t *blocks_per_lane,
+                          int32_t *lds_bytes)
+{
+    if (!b) return MUCA_E_INVAL;
+    if (waves_per_walker)
+        for (size_t k = 0; k < b->jobs.size(); ++k) waves_per_walker[k] = tile_wpw(b, b->wpw, k);
+    if (blocks_per_lane) *blocks_per_lane = b->bpl;
+    if (lds_bytes) *lds_bytes = (int32_t)(batch_lds(b, b->wpw) + b->tab_bytes);
     return MUCA_OK;
 }
 

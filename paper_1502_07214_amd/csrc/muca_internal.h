@@ -90,6 +90,7 @@ struct BatchJob {
     int cls[kMaxClasses + 1];
     uint32_t k0, k1;
     int lds_tables;          // 1: thresholds and neighbour table staged in LDS for this job's tiles
+    int wpw;                 // waves per walker of this job's tiles (1 or 4) in a per-job launch
 };
 
 struct BatchArgs {

@@ -554,8 +554,25 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
 // first.  Spins are staged in LDS; thresholds and neighbour tables too for
 // the jobs whose tables fit the batch's LDS budget (else they are read through
 // the caches); histograms go straight to each job's buffer.  Each walker
-// runs exactly the chain it runs in its own job's launch.
+// runs exactly the chain it runs in its own job's launch.  WPW == 0 takes the
+// waves per walker from each tile's job (1 or 4), so the walkers of large
+// lattices get a whole block while small ones share one.
 // ---------------------------------------------------------------------------
+template <int WPW, int BPL, bool RECORD>
+__device__ __forceinline__ void batch_tile(const BatchArgs &b, const BatchJob &J, SweepArgs &a, int walker0,
+                                           unsigned char *smem)
+{
+    if (J.lds_tables) {
+        a.lds_off_r = b.lds_off_tab;
+        a.lds_off_nb = b.lds_off_tab + ((16 * (J.V + 1 + 2 * kRPad) + 15) & ~15);
+        sweep_tile<WPW, BPL, RECORD, true, 0>(a, walker0, smem);
+    } else {
+        a.lds_off_r = 0;
+        a.lds_off_nb = 0;
+        sweep_tile<WPW, BPL, RECORD, false, 0>(a, walker0, smem);
+    }
+}
+
 template <int WPW, int BPL, bool RECORD>
 __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
 {
@@ -593,14 +610,13 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
         a.lds_hist = 0;
         a.lds_off_hist = kLdsFixed;
         a.lds_off_lat = b.lds_off_lat;
-        if (J.lds_tables) {
-            a.lds_off_r = b.lds_off_tab;
-            a.lds_off_nb = b.lds_off_tab + ((16 * (J.V + 1 + 2 * kRPad) + 15) & ~15);
-            sweep_tile<WPW, BPL, RECORD, true, 0>(a, tile.y, smem);
+        if constexpr (WPW == 0) {
+            if (J.wpw == 4)
+                batch_tile<4, BPL, RECORD>(b, J, a, tile.y, smem);
+            else
+                batch_tile<1, BPL, RECORD>(b, J, a, tile.y, smem);
         } else {
-            a.lds_off_r = 0;
-            a.lds_off_nb = 0;
-            sweep_tile<WPW, BPL, RECORD, false, 0>(a, tile.y, smem);
+            batch_tile<WPW, BPL, RECORD>(b, J, a, tile.y, smem);
         }
     }
 }
@@ -912,6 +928,10 @@ static hipError_t launch_batch_t(const BatchArgs &b, size_t lds, int blocks, hip
 
 hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, size_t lds, int blocks, hipStream_t s)
 {
+    if (wpw == 0) {
+        if (bpl == 1) return record ? launch_batch_t<0, 1, true>(b, lds, blocks, s) : launch_batch_t<0, 1, false>(b, lds, blocks, s);
+        return record ? launch_batch_t<0, 2, true>(b, lds, blocks, s) : launch_batch_t<0, 2, false>(b, lds, blocks, s);
+    }
     if (wpw == 1) {
         if (bpl == 1) return record ? launch_batch_t<1, 1, true>(b, lds, blocks, s) : launch_batch_t<1, 1, false>(b, lds, blocks, s);
         return record ? launch_batch_t<1, 2, true>(b, lds, blocks, s) : launch_batch_t<1, 2, false>(b, lds, blocks, s);

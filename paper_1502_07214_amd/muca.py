@@ -29,7 +29,7 @@ EXPORTS = (
     "muca_set_weights", "muca_get_weights", "muca_reweight", "muca_read_state", "muca_write_state",
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
-    "muca_batch_set_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
+    "muca_batch_set_launch", "muca_batch_get_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
     "muca_reweight_hist", "muca_set_recursion",
 )
 
@@ -94,6 +94,7 @@ def lib():
     L.muca_batch_query_size.argtypes = [P(vp), i32, sz]
     L.muca_batch_create.argtypes = [P(vp), i32, vp, ctypes.c_size_t, P(vp)]
     L.muca_batch_set_launch.argtypes = [vp, i32, i32, i32]
+    L.muca_batch_get_launch.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.muca_batch_sweep.argtypes = [vp, i64, u32]
     L.muca_batch_free.argtypes = [vp]
     L.muca_batch_free.restype = None
@@ -328,6 +329,13 @@ class MucaBatch:
 
     def set_launch(self, waves_per_walker: int, blocks_per_lane: int, blocks: int = 0):
         _check(lib().muca_batch_set_launch(self._h, waves_per_walker, blocks_per_lane, blocks), "muca_batch_set_launch")
+
+    def get_launch(self) -> dict:
+        """The shape in use: waves per walker of each job (in the order given), blocks per lane, LDS bytes."""
+        w = (ctypes.c_int32 * len(self.jobs))()
+        b, lds = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().muca_batch_get_launch(self._h, w, ctypes.byref(b), ctypes.byref(lds)), "muca_batch_get_launch")
+        return {"waves_per_walker": list(w), "blocks_per_lane": b.value, "lds_bytes": lds.value}
 
     def sweep(self, n_sweeps: int, record: bool = False):
         _check(lib().muca_batch_sweep(self._h, int(n_sweeps), MUCA_RECORD if record else 0), "muca_batch_sweep")

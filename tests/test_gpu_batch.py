@@ -23,7 +23,7 @@ def iterate(jobs, sweep, iterations, sweeps):
     return hists
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (2, 1), (4, 1), (4, 2)])
+@pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1), (4, 1), (4, 2)])
 def test_batch_equals_plain(shape):
     print(f"[batch] mixed jobs {MIX} shape {shape}", flush=True)
     a = [MucaJob(L, T, nw, seed=s, max_delta=4) for (L, T, nw, s) in MIX]
@@ -106,4 +106,64 @@ def test_batch_mixes_staged_and_cached_tables(shape):
         assert ja.lnW.tobytes() == jb.lnW.tobytes()
     batch.free()
     for j in a + b:
+        j.free()
+
+
+# Large lattices with few walkers next to small ones: the per-job launch
+# shape (waves per walker 0) gives the L=16 and L=14 walkers four waves each
+# and the small jobs one, in the same launch.
+PER_JOB_MIX = [(16, 2.0, 5, 31), (4, 1.0, 9, 14), (14, 1.0, 3, 32), (5, 2.0, 6, 12), (8, 0.9, 7, 11), (7, 1.4182, 4, 15)]
+
+
+@pytest.mark.parametrize("bpl", [1, 2])
+def test_batch_per_job_waves_per_walker(bpl):
+    print(f"[batch] per-job waves per walker {PER_JOB_MIX} bpl {bpl}", flush=True)
+    a = [MucaJob(L, T, nw, seed=s, max_delta=3) for (L, T, nw, s) in PER_JOB_MIX]
+    b = [MucaJob(L, T, nw, seed=s, max_delta=3) for (L, T, nw, s) in PER_JOB_MIX]
+    batch = MucaBatch(a)
+    assert batch.get_launch()["waves_per_walker"] == [1] * len(PER_JOB_MIX)
+    batch.set_launch(0, bpl)
+    shape = batch.get_launch()
+    assert shape["waves_per_walker"] == [4, 1, 4, 1, 1, 1] and shape["blocks_per_lane"] == bpl
+    ha = iterate(a, batch.sweep, 3, 30)
+    hb = iterate(b, lambda n: [j.sweep(n) for j in b], 3, 30)
+    for it in range(3):
+        for x, y in zip(ha[it], hb[it]):
+            assert np.array_equal(x, y)
+    batch.sweep(20, record=True)
+    for j in b:
+        j.sweep(20, record=True)
+    for ja, jb in zip(a, b):
+        sa, sta = ja.read_state()
+        sb, stb = jb.read_state()
+        assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+        assert ja.lnW.tobytes() == jb.lnW.tobytes()
+        assert ja.read_accum() == jb.read_accum()
+    batch.free()
+    for j in a + b:
+        j.free()
+
+
+def test_batch_per_job_matches_oracle():
+    mix = [(14, 1.0, 2, 41), (4, 2.0, 5, 42), (6, 1.0, 3, 43)]
+    print(f"[batch] per-job waves per walker vs oracle {mix}", flush=True)
+    jobs = [MucaJob(L, T, nw, seed=s, max_delta=1) for (L, T, nw, s) in mix]
+    batch = MucaBatch(jobs)
+    batch.set_launch(0, 1)
+    assert batch.get_launch()["waves_per_walker"] == [4, 1, 1]
+    orcs = [oracle.OracleJob(L, T, nw, s) for (L, T, nw, s) in mix]
+    for it in range(2):
+        batch.sweep(6)
+        for j, o in zip(jobs, orcs):
+            h = j.reduce_hist()
+            j.update_weights(h)
+            o.sweep(6)
+            ho = o.take_hist()
+            o.update_weights(ho)
+            assert np.array_equal(h, ho)
+    for j, o in zip(jobs, orcs):
+        s, st = j.read_state()
+        assert np.array_equal(s, o.spins) and np.array_equal(st, o.state)
+    batch.free()
+    for j in jobs:
         j.free()
