@@ -132,8 +132,8 @@ int muca_reduce_hist(muca_job *job, int64_t *hist_host, int32_t reset);
 
 /* Step "update" (Sec. II, iterative weights): lnW[E] -= log(H[E]) where H[E] > 0
  * (plain recursion W <- W / H; muca_set_recursion selects a variant) on the
- * job's weights, then re-upload the
- * threshold tables.  hist (V+1, non-negative) is the merged histogram of the
+ * job's weights, then re-upload the threshold tables.
+ * hist (V+1, non-negative) is the merged histogram of the
  * iteration; lnW_out (V+1, may be NULL) receives the new weights; flatness_out
  * (may be NULL) receives min_E H[E] / mean_E H[E] over [0, V] of hist.  The
  * production sums are cleared (they belong to the weights they were sampled
@@ -253,7 +253,8 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
 /* Launch shape of the batched kernel (results do not depend on it):
  * waves_per_walker in {0, 1, 2, 4}, blocks_per_lane in {1, 2}; blocks <= 0
  * fills the device (occupancy query).  The default is one wave per walker for
- * every job.  waves_per_walker 0 picks per job: four waves per walker for the
+ * every job (two or four when four lattices of the largest job do not fit in
+ * the LDS of a block).  waves_per_walker 0 picks per job: four waves per walker for the
  * jobs whose walkers would otherwise set the length of the launch (large
  * lattices, few waves in the batch), one for the rest; it pays while the
  * weights are smooth.  MUCA_E_SIZE if the lattice slots of the largest tile
