@@ -33,6 +33,8 @@ POINTS = (
     (16, 2.0, 1024, 4000, 600, 8, 10000),
     (16, 1.0, 1024, 4000, 1500, 8, 10000),
     (20, 2.0, 1024, 4000, 800, 8, 10000),
+    (20, 1.0, 1024, 4000, 1500, 8, 10000),
+    (24, 2.0, 1024, 4000, 1200, 8, 10000),
 )
 FIRST_ORDER_T = 1.4182  # below the tricritical temperature the transition is first order
 
