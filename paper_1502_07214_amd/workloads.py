@@ -67,7 +67,8 @@ def batched_jobs(spec=BATCHED) -> list:
     counts = {}
     for p in picks:
         counts[combos[p]] = counts.get(combos[p], 0) + spec["group_walkers"]
-    return [(L, T, n, 1000 * L + int(round(T * 1e4))) for (L, T), n in sorted(counts.items())]
+    # one Philox key per (L, T): 10^4 T < 10^5 for every temperature here, so the map is one-to-one
+    return [(L, T, n, 100_000 * L + int(round(T * 1e4))) for (L, T), n in sorted(counts.items())]
 
 
 # Served: Poisson arrivals (mean 20 jobs/s) of MUCA jobs, weights tilted to

@@ -1,0 +1,116 @@
+"""Host-side sequencing that needs no GPU: request streams, transition fields,
+tilted starts, the jackknife, the campaign's convergence loop and brackets, the
+batched job table, and the library's host-only flatness measure."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1502_07214_amd import analysis, campaign, workloads
+from paper_1502_07214_amd.muca import muca_flatness
+from paper_1502_07214_amd.serve import TRANSITION, delta_mid, poisson_requests, tilted_weights
+
+
+def test_delta_mid_hits_the_paper_fields_and_interpolates():
+    for T, d in TRANSITION:
+        assert delta_mid(T) == d
+    (t0, d0), (t1, d1) = TRANSITION[1], TRANSITION[2]
+    assert delta_mid(0.5 * (t0 + t1)) == pytest.approx(0.5 * (d0 + d1), rel=1e-15)
+    # outside the tabulated range the end values hold
+    assert delta_mid(0.5) == TRANSITION[0][1] and delta_mid(3.0) == TRANSITION[-1][1]
+
+
+def test_tilted_weights_are_the_canonical_ensemble_at_delta_mid():
+    L, T = 5, 1.2
+    w = tilted_weights(L, T)
+    assert w.shape == (L ** 3 + 1,) and w[0] == 0.0
+    # exp(lnW(E+1) - lnW(E)) = exp(-beta Delta_mid): the Boltzmann factor of one more occupied site
+    assert np.allclose(np.diff(w), -delta_mid(T) / T, rtol=1e-13, atol=0)
+
+
+def test_poisson_requests_are_seeded_and_well_formed():
+    a = poisson_requests(500, 20.0, seed=3, L_range=(8, 24), walker_choices=(64, 128))
+    b = poisson_requests(500, 20.0, seed=3, L_range=(8, 24), walker_choices=(64, 128))
+    assert [(r.L, r.T, r.n_walkers, r.seed, r.arrival) for r in a] == [(r.L, r.T, r.n_walkers, r.seed, r.arrival) for r in b]
+    arr = np.array([r.arrival for r in a])
+    assert arr[0] == 0.0 and np.all(np.diff(arr) >= 0)
+    assert {r.L for r in a} <= set(range(8, 25)) and {r.n_walkers for r in a} <= {64, 128}
+    assert all(0.9 <= r.T <= 2.0 for r in a)
+    assert len({r.seed for r in a}) == len(a)
+    # exponential gaps: the mean gap of 20000 arrivals is within 3 % of 1/rate
+    many = poisson_requests(20000, 20.0, seed=1)
+    gaps = np.diff([r.arrival for r in many])
+    assert abs(gaps.mean() * 20.0 - 1.0) < 0.03
+
+
+def test_jackknife_of_leave_one_out_means_is_the_standard_error():
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=12)
+    loo = [(x.sum() - xi) / (len(x) - 1) for xi in x]
+    m, e = analysis.jackknife(loo)
+    assert m == pytest.approx(x.mean(), rel=1e-12)
+    assert e == pytest.approx(x.std(ddof=1) / math.sqrt(len(x)), rel=1e-12)
+
+
+def test_block_sums_subtract_exactly():
+    a = {"H": [5, 7], "SJ": [2 ** 62, -3], "V": 1}
+    b = {"H": [1, 7], "SJ": [2 ** 62 - 1, -4], "V": 1}
+    assert analysis._minus(a, b) == {"H": [4, 0], "SJ": [1, 1], "V": 1}
+
+
+def test_bracket_around_the_scan_maximum():
+    g = np.linspace(0.0, 1.0, 11)
+    assert campaign._bracket(g, -(g - 0.3) ** 2) == (0.2, 0.4, 3)
+    assert campaign._bracket(g, g) == (0.9, 1.0, 10)  # maximum at the edge: bracket clipped
+    assert campaign._bracket(g, -g) == (0.0, 0.1, 0)
+
+
+class _FakeJob:
+    """Stands in for MucaJob in the convergence loop: hands out a fixed
+    sequence of histograms and records the updates it is asked for."""
+
+    def __init__(self, V, hists):
+        self.V, self.hists, self.updates, self.sweeps = V, list(hists), [], 0
+
+    def sweep(self, n):
+        self.sweeps += n
+
+    def reduce_hist(self, reset=True):
+        return np.asarray(self.hists.pop(0), dtype=np.int64)
+
+    def update_weights(self, h):
+        self.updates.append(h.copy())
+
+
+def test_converge_stops_at_the_first_flat_iteration():
+    V = 3
+    rough, flat = [1, 9, 9, 9], [6, 5, 7, 6]
+    job = _FakeJob(V, [rough, rough, flat, rough])
+    out = campaign.converge(job, sweeps=10, cap=10)
+    assert out == {"iterations": 3, "flatness": muca_flatness(np.array(flat), 0, V), "flat": True}
+    assert len(job.updates) == 2 and job.sweeps == 30  # no update after the flat one
+
+
+def test_converge_respects_the_cap():
+    job = _FakeJob(2, [[0, 4, 4]] * 5)
+    out = campaign.converge(job, sweeps=1, cap=5)
+    assert out["iterations"] == 5 and not out["flat"] and len(job.updates) == 5
+
+
+def test_batched_workload_table():
+    jobs = workloads.batched_jobs()
+    spec = workloads.BATCHED
+    assert sum(n for (_, _, n, _) in jobs) == spec["groups"] * spec["group_walkers"]
+    assert all(n % spec["group_walkers"] == 0 for (_, _, n, _) in jobs)
+    assert len({(L, T) for (L, T, _, _) in jobs}) == len(jobs)  # one job per (L, T)
+    assert all(L in spec["Ls"] and T in spec["Ts"] for (L, T, _, _) in jobs)
+    assert len({s for (_, _, _, s) in jobs}) == len(jobs)
+    assert jobs == workloads.batched_jobs()
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 9), (2, 5), (4, 4)])
+def test_host_flatness_is_min_over_mean(lo, hi):
+    h = np.array([3, 8, 5, 9, 4, 7, 6, 2, 10, 1], dtype=np.int64)
+    w = h[lo:hi + 1]
+    assert muca_flatness(h, lo, hi) == pytest.approx(w.min() / w.mean(), rel=1e-15)
+    assert muca_flatness(np.zeros(10, dtype=np.int64), lo, hi) == 0.0
