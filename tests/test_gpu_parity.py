@@ -138,6 +138,56 @@ def test_truncated_l12_t2_w256():
              workloads.delta_grid(w["deltas"]))
 
 
+def test_full_size_benchmark_job_sampled():
+    """The benchmark job at full size and in the benchmark's launch shape
+    (256 walkers, 30 x 10^4 sweeps, 10^4 production sweeps, 200 Delta).  The
+    oracle cannot replay all of it in seconds, so: walkers sampled across the
+    job are replayed on the oracle through the last iteration, from the GPU's
+    state and weights, and must end bit-identical; every walker's tracked
+    E_J, E_Delta, M equals a recomputation from its spins; every merged
+    histogram counts each sweep of each walker once and contains the sampled
+    walkers' own entries; the reweighting of the GPU's full production sums
+    matches the oracle's reweighting of the same sums."""
+    w = workloads.workload("l12_t2_w256")
+    L, T, nw, S = w["L"], w["T"], w["n_walkers"], w["sweeps"]
+    deltas = workloads.delta_grid(w["deltas"])
+    say(f"[parity] full-size benchmark job L={L} T={T} walkers={nw} {w['iterations']}x{S} + {w['production']}")
+    job = MucaJob(L, T, nw, seed=w["seed"], max_delta=len(deltas))
+    for it in range(w["iterations"] - 1):
+        job.sweep(S)
+        h = job.reduce_hist(reset=True)
+        assert h.sum() == nw * S and h.min() >= 0
+        job.update_weights(h)
+    spins0, state0 = job.read_state()
+    lnW0 = job.lnW.copy()
+    job.sweep(S)
+    h = job.reduce_hist(reset=True)
+    assert h.sum() == nw * S
+    spins1, state1 = job.read_state()
+    assert np.all(state1[:, 3] == w["iterations"] * S)
+    for k in range(nw):
+        assert oracle.energies(L, spins1[k]) == tuple(int(x) for x in state1[k, :3]), f"walker {k} energies"
+    part = np.zeros_like(h)
+    for k in (0, 97, 255):
+        o = oracle.OracleJob(L, T, 1, w["seed"], lnW=lnW0, first_walker=k)
+        o.spins[0] = spins0[k]
+        o.state[0] = state0[k]
+        o.sweep(S)
+        assert np.array_equal(o.spins[0], spins1[k]), f"walker {k} lattice differs after the last iteration"
+        assert np.array_equal(o.state[0], state1[k]), f"walker {k} state differs after the last iteration"
+        part += o.take_hist()
+    assert np.all(h - part >= 0), "the merged histogram lacks entries of a sampled walker"
+    job.update_weights(h)
+    job.sweep(w["production"], record=True)
+    assert job.reduce_hist(reset=True).sum() == nw * w["production"]
+    sums = job.read_accum()
+    assert sum(sums["H"]) == nw * w["production"]
+    g = job.reweight(deltas)
+    r = oracle.reweight(L ** 3, oracle.beta_of(T), job.lnW, sums, deltas)
+    assert_obs_close(g, r, oracle.beta_of(T), L ** 3, abs_moments(sums, job.lnW, oracle.beta_of(T), deltas))
+    job.free()
+
+
 def test_truncated_l16_t1_w1024():
     """L=16, T=1.0, all 1024 walkers, 2 iterations x 100 sweeps + 100 production."""
     w = workloads.workload("l16_t1_w1024", truncated=True)
