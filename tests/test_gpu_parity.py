@@ -138,17 +138,19 @@ def test_truncated_l12_t2_w256():
              workloads.delta_grid(w["deltas"]))
 
 
-def test_full_size_benchmark_job_sampled():
-    """The benchmark job at full size and in the benchmark's launch shape
-    (256 walkers, 30 x 10^4 sweeps, 10^4 production sweeps, 200 Delta).  The
-    oracle cannot replay all of it in seconds, so: walkers sampled across the
-    job are replayed on the oracle through the last iteration, from the GPU's
-    state and weights, and must end bit-identical; every walker's tracked
-    E_J, E_Delta, M equals a recomputation from its spins; every merged
-    histogram counts each sweep of each walker once and contains the sampled
-    walkers' own entries; the reweighting of the GPU's full production sums
-    matches the oracle's reweighting of the same sums."""
-    w = workloads.workload("l12_t2_w256")
+@pytest.mark.parametrize("name", ["l12_t2_w256", "l16_t1_w1024"])
+def test_full_size_benchmark_job_sampled(name):
+    """A job at full size and in the default launch shape (the benchmark's:
+    L=12, 256 walkers, 30 x 10^4 sweeps, 10^4 production sweeps, 200 Delta;
+    and L=16, T=1, 1024 walkers, 60 x 2 10^4 sweeps).  The oracle cannot
+    replay all of it in seconds, so: walkers sampled across the job are
+    replayed on the oracle through the last iteration, from the GPU's state
+    and weights, and must end bit-identical; every walker's tracked E_J,
+    E_Delta, M equals a recomputation from its spins; every merged histogram
+    counts each sweep of each walker once and contains the sampled walkers'
+    own entries; the reweighting of the GPU's full production sums matches
+    the oracle's reweighting of the same sums."""
+    w = workloads.workload(name)
     L, T, nw, S = w["L"], w["T"], w["n_walkers"], w["sweeps"]
     deltas = workloads.delta_grid(w["deltas"])
     say(f"[parity] full-size benchmark job L={L} T={T} walkers={nw} {w['iterations']}x{S} + {w['production']}")
@@ -168,7 +170,7 @@ def test_full_size_benchmark_job_sampled():
     for k in range(nw):
         assert oracle.energies(L, spins1[k]) == tuple(int(x) for x in state1[k, :3]), f"walker {k} energies"
     part = np.zeros_like(h)
-    for k in (0, 97, 255):
+    for k in (0, nw // 3 + 12, nw - 1):
         o = oracle.OracleJob(L, T, 1, w["seed"], lnW=lnW0, first_walker=k)
         o.spins[0] = spins0[k]
         o.state[0] = state0[k]
