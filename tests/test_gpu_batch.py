@@ -167,3 +167,54 @@ def test_batch_per_job_matches_oracle():
     batch.free()
     for j in jobs:
         j.free()
+
+
+def test_full_size_batched_workload_sampled():
+    """The batched workload at full size (19 jobs of mixed L and T, 4096
+    walkers, 10 iterations x 1000 sweeps, one persistent launch per iteration
+    in the default shape): in every job the histograms count each sweep of
+    each walker once and every walker's tracked E_J, E_Delta, M equals a
+    recomputation from its spins; the first and the last walker of the largest
+    and the smallest lattice's jobs, and of one in between, are replayed on the
+    oracle through the last iteration from the GPU's state and weights and end
+    bit-identical, their entries contained in the merged histogram."""
+    from paper_1502_07214_amd import workloads
+    specs = workloads.batched_jobs()
+    it, sw = workloads.BATCHED["iterations"], workloads.BATCHED["sweeps"]
+    print(f"[batch] full-size batched workload: {len(specs)} jobs, {sum(n for _, _, n, _ in specs)} walkers, {it}x{sw}",
+          flush=True)
+    jobs = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
+    batch = MucaBatch(jobs)
+    for k in range(it - 1):
+        batch.sweep(sw)
+        for j, (L, T, n, s) in zip(jobs, specs):
+            h = j.reduce_hist(reset=True)
+            assert h.sum() == n * sw
+            j.update_weights(h)
+    before = [(j.read_state(), j.lnW.copy()) for j in jobs]
+    batch.sweep(sw)
+    picks = sorted(range(len(specs)), key=lambda x: specs[x][0])
+    picks = [picks[0], picks[len(picks) // 2], picks[-1]]
+    for x, (j, (L, T, n, s)) in enumerate(zip(jobs, specs)):
+        h = j.reduce_hist(reset=True)
+        assert h.sum() == n * sw
+        spins, state = j.read_state()
+        assert np.all(state[:, 3] == it * sw)
+        for w in range(n):
+            assert oracle.energies(L, spins[w]) == tuple(int(v) for v in state[w, :3]), f"job {x} walker {w}"
+        if x not in picks:
+            continue
+        (spins0, state0), lnW0 = before[x]
+        part = np.zeros_like(h)
+        for w in (0, n - 1):
+            o = oracle.OracleJob(L, T, 1, s, lnW=lnW0, first_walker=w)
+            o.spins[0] = spins0[w]
+            o.state[0] = state0[w]
+            o.sweep(sw)
+            assert np.array_equal(o.spins[0], spins[w]) and np.array_equal(o.state[0], state[w]), \
+                f"job (L={L}, T={T}) walker {w} differs after the last iteration"
+            part += o.take_hist()
+        assert np.all(h - part >= 0)
+    batch.free()
+    for j in jobs:
+        j.free()
