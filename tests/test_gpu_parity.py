@@ -190,6 +190,32 @@ def test_full_size_benchmark_job_sampled(name):
     job.free()
 
 
+def test_saturation_job_sampled():
+    """The saturation job at full size in its launch shape (65 536 walkers at
+    L=8, one wave each, thresholds read through the caches; 10 + 100 sweeps
+    under flat weights): sampled walkers replayed on the oracle from their
+    initial state end bit-identical, every walker's energies equal a
+    recomputation, and the histogram counts every sweep of every walker."""
+    s = workloads.SATURATION
+    L, T, nw = s["L"], s["T"], s["n_walkers"]
+    say(f"[parity] saturation job L={L} walkers={nw}")
+    job = MucaJob(L, T, nw, seed=s["seed"], max_delta=1)
+    job.sweep(10)
+    job.sweep(s["sweeps"])
+    h = job.reduce_hist(reset=True)
+    assert h.sum() == nw * (10 + s["sweeps"])
+    spins, state = job.read_state()
+    assert np.all(state[:, 3] == 10 + s["sweeps"])
+    for w in range(0, nw, 97):
+        assert oracle.energies(L, spins[w]) == tuple(int(v) for v in state[w, :3]), f"walker {w}"
+    for w in (0, 4097, 33333, nw - 1):
+        o = oracle.OracleJob(L, T, 1, s["seed"], first_walker=w)
+        o.sweep(10)
+        o.sweep(s["sweeps"])
+        assert np.array_equal(o.spins[0], spins[w]) and np.array_equal(o.state[0], state[w]), f"walker {w}"
+    job.free()
+
+
 def test_truncated_l16_t1_w1024():
     """L=16, T=1.0, all 1024 walkers, 2 iterations x 100 sweeps + 100 production."""
     w = workloads.workload("l16_t1_w1024", truncated=True)
