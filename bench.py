@@ -138,7 +138,8 @@ def served_leg():
     for mode, fn, c in (("served", serve, cfg), ("plain", serve_plain, cfg), ("served_fast_recursion", serve, fast)):
         r = fn(reqs, c)
         out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "makespan_s", "jobs_per_s", "attempts_per_s",
-                                       "latency_p50_s", "latency_p99_s", "iterations_p50", "queue_depth_max")}
+                                       "latency_p50_s", "latency_p99_s", "latency_converged_p50_s",
+                                       "latency_converged_p99_s", "iterations_p50", "queue_depth_max")}
     return out
 
 

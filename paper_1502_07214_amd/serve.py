@@ -250,6 +250,9 @@ def _summary(records, makespan, attempts, launches, depth, kept) -> dict:
         "launches": launches,
         "latency_p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
         "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+        # the same over the jobs that reached a flat histogram (censored jobs left out)
+        "latency_converged_p50_s": float(np.percentile([r.latency for r in conv], 50)) if conv else math.nan,
+        "latency_converged_p99_s": float(np.percentile([r.latency for r in conv], 99)) if conv else math.nan,
         "iterations_p50": float(np.percentile([r.iterations for r in records.values()], 50)) if records else 0,
         "queue_depth_max": int(max(depth)) if depth else 0,
         "queue_depth_mean": float(np.mean(depth)) if depth else 0.0,

@@ -1,6 +1,7 @@
 """Host-side sequencing that needs no GPU: request streams, transition fields,
 tilted starts, the jackknife, the campaign's convergence loop and brackets, the
-batched job table, and the library's host-only flatness measure."""
+batched job table, the serving summary, and the library's host-only flatness
+measure."""
 import math
 
 import numpy as np
@@ -114,3 +115,16 @@ def test_host_flatness_is_min_over_mean(lo, hi):
     w = h[lo:hi + 1]
     assert muca_flatness(h, lo, hi) == pytest.approx(w.min() / w.mean(), rel=1e-15)
     assert muca_flatness(np.zeros(10, dtype=np.int64), lo, hi) == 0.0
+
+
+def test_serve_summary_separates_censored_jobs():
+    from paper_1502_07214_amd.serve import JobRecord, Request, _summary
+    recs = {}
+    for i, (lat, conv) in enumerate([(1.0, True), (2.0, True), (3.0, True), (50.0, False)]):
+        r = JobRecord(Request(i, 8, 1.0, 64, i, 0.0), admitted=0.0, finished=lat, iterations=10, converged=conv)
+        recs[i] = r
+    out = _summary(recs, makespan=50.0, attempts=100, launches=4, depth=[0, 2, 1], kept={})
+    assert out["converged"] == 3 and out["censored"] == 1
+    assert out["latency_p99_s"] == pytest.approx(np.percentile([1, 2, 3, 50], 99))
+    assert out["latency_converged_p99_s"] == pytest.approx(np.percentile([1, 2, 3], 99))
+    assert out["latency_converged_p50_s"] == 2.0 and out["queue_depth_max"] == 2
