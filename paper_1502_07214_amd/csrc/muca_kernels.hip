@@ -21,7 +21,9 @@
 //    writes are whole dwords with no atomics.  Thresholds B', R_+-, and the
 //    neighbour table sit in LDS when they fit, else are read through L1/L2.
 //  * Histograms: one LDS atomic per walker per sweep, flushed to HBM with one
-//    64-bit atomic per nonzero bin at the end of the launch.
+//    64-bit atomic per nonzero bin at the end of the launch (when the histogram
+//    fits in LDS next to the lattices; otherwise, and in batched launches, one
+//    64-bit HBM atomic per walker per sweep).
 #include <hip/hip_runtime.h>
 
 #include "muca_internal.h"
@@ -348,7 +350,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     const int V = a.V, Vp = a.Vp;
     const int tid = threadIdx.x;
     W wk;
-    wk.wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: say so
+    wk.wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave, held in a scalar register
     wk.lane = tid & 63;
     wk.slot = wk.wave / WPW;
     wk.wi = wk.wave % WPW;
