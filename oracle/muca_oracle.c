@@ -13,8 +13,8 @@
  * after another (threads only split the independent walkers), one site visit
  * after another, one Philox block evaluated per site visit.
  *
- * Conventions (the paper is silent on these; the readings are listed in the
- * design notes of the repository and restated at each function):
+ * Conventions (the paper is silent on these; each is restated at the function
+ * that uses it):
  *   site index      i = x + L*(y + L*z), periodic neighbours x+-1, y+-1, z+-1
  *   colour-major    visiting order (even L: 2 colours, odd L: 3 colours)
  *   proposal        sigma' = b-th of the two other values, ascending

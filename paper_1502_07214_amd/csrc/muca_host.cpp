@@ -222,7 +222,7 @@ bool plan_launch(const muca_job *j, int wpw, int bpl, int lds_tables_req, Launch
 
 void default_launch(muca_job *j)
 {
-    // Measured on MI355X (see the design notes): few walkers -> spread each
+    // Measured on MI355X: few walkers -> spread each
     // walker over a whole block (4 waves) with the thresholds staged in LDS;
     // many walkers -> one wave per walker, thresholds read through the caches
     // (LDS then only holds lattices, so more blocks fit per CU).  One Philox
