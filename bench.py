@@ -217,7 +217,23 @@ def cpu_baseline(w, deltas):
     return {"value": t["attempts"] / dt, "unit": "attempts/s", "cores": o.threads_used, "kind": "oracle",
             "sample": f"{t['name']}: all {t['n_walkers']} walkers, {t['iterations']} x {t['sweeps']} sweeps + "
                       f"{t['production']} production sweeps + reweight to {len(deltas)} Delta "
-                      f"({t['attempts']:.3e} attempts, {dt:.1f} s)"}
+                      f"({t['attempts']:.3e} attempts, {dt:.1f} s)",
+            "host": host_cpu()}
+
+
+def host_cpu() -> str:
+    """CPU model and logical CPU count of the host that timed the oracle."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
 
 
 def main():
