@@ -49,11 +49,11 @@ REC_EXTRAPOLATE, REC_ACC_EXT = 2, 3
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=WORKLOAD)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gpus", type=int, default=1, help="number of GPUs (only 1 is supported)")
+    ap.add_argument("--steps", type=int, default=3, help="timed steps (one whole job each)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed steps before the timed ones")
+    ap.add_argument("--workload", default=WORKLOAD, help="plain workload a step runs (default: the benchmark job)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, saturation, served and convergence legs")
     ap.add_argument("--launch", default=None, help="wpw,bpl,lds_tables (default: library's choice)")
     return ap.parse_args()
