@@ -11,8 +11,9 @@ window) or it hits the iteration cap (then it is reported as censored).
 Continuous batching: jobs are admitted from a FIFO queue while the resident
 walker count and device-memory footprint allow; every iteration of the loop is
 one persistent batched launch (MucaBatch) over all resident jobs, whatever
-their size; finished jobs leave and queued ones join at the next launch, so
-their work overlaps on the device.  Walker state stays resident in HBM for a
+their size (a job resident alone runs its own launch instead); finished jobs
+leave and queued ones join at the next launch, so their work overlaps on the
+device.  Walker state stays resident in HBM for a
 job's whole life.  The per-job chain does not depend on the mix: a job served
 among others gives bit-identical results to the same job run alone.
 
@@ -175,21 +176,30 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
         if not active:
             _wait_until(t0, pending[0].arrival)
             continue
-        if changed or batch is None:
+        if len(active) == 1:
+            # a lone job runs its own launch (its shape keeps neighbour
+            # positions in registers and spreads few walkers over whole blocks)
             if batch is not None:
                 batch.free()
-            batch = MucaBatch([a.job for a in active])
-            if cfg.shape:
-                batch.set_launch(*cfg.shape)
-        batch.sweep(cfg.sweeps)
+                batch = None
+            active[0].job.sweep(cfg.sweeps)
+        else:
+            if changed or batch is None:
+                if batch is not None:
+                    batch.free()
+                batch = MucaBatch([a.job for a in active])
+                if cfg.shape:
+                    batch.set_launch(*cfg.shape)
+            batch.sweep(cfg.sweeps)
         launches += 1
         attempts += sum(a.rec.req.n_walkers * a.V for a in active) * cfg.sweeps
         torch.cuda.current_stream().synchronize()
         now = time.perf_counter() - t0
         done = [a for a in active if a.step_done(cfg, now)]
         if done:
-            batch.free()
-            batch = None
+            if batch is not None:
+                batch.free()
+                batch = None
             if progress is not None:
                 progress([a.rec for a in done])
             for a in done:

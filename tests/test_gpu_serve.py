@@ -40,3 +40,26 @@ def test_admission_respects_capacity():
     recs = sorted(out["records"].values(), key=lambda r: r.admitted)
     for k in range(2, len(recs)):
         assert recs[k].admitted >= min(x.finished for x in recs[:k]) - 1e-9
+
+
+def test_lone_and_batched_launches_alternate():
+    """A slow stream: a job runs alone (its own launch) until the next one
+    arrives, then in a batch, then alone again; its chain is the same as when
+    it is served by itself."""
+    reqs = [Request(0, 6, 1.0, 64, 11, 0.0), Request(1, 5, 2.0, 64, 12, 0.05), Request(2, 4, 1.4182, 64, 13, 0.1)]
+    cfg = ServeConfig(sweeps=50, threshold=0.99, max_iterations=60, max_walkers=512)
+    print("[serve] lone / batched alternation", flush=True)
+    mix = serve(reqs, cfg, keep_jobs=True)
+    assert mix["jobs"] == 3 and mix["censored"] == 3
+    for r in reqs:
+        alone = serve_plain([Request(r.id, r.L, r.T, r.n_walkers, r.seed, 0.0)], cfg, keep_jobs=True)
+        a, b = mix["records"][r.id], alone["records"][r.id]
+        assert a.iterations == b.iterations == 60 and a.flatness == b.flatness
+        ja, jb = mix["jobs_kept"][r.id], alone["jobs_kept"][r.id]
+        sa, sta = ja.read_state()
+        sb, stb = jb.read_state()
+        assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+        assert ja.lnW.tobytes() == jb.lnW.tobytes()
+        jb.free()
+    for j in mix["jobs_kept"].values():
+        j.free()
