@@ -36,6 +36,7 @@ POINTS = (
     (20, 1.0, 1024, 4000, 1500, 8, 10000),
     (24, 2.0, 1024, 4000, 1200, 8, 10000),
     (28, 2.0, 1024, 4000, 1500, 8, 10000),
+    (24, 1.0, 1024, 4000, 1500, 8, 10000),
     (8, 0.9, 512, 1000, 1500, 8, 5000),
     (12, 0.9, 512, 2000, 1500, 8, 10000),
     (16, 0.9, 1024, 4000, 1500, 8, 10000),
