@@ -1,7 +1,8 @@
 """Small-L campaign of the paper's observables (Sec. III at small sizes).
 
 For each (L, T): weights converged to a flat E_Delta histogram (start tilted
-towards the transition field, accumulated + extrapolating recursion), a
+towards the transition field, accumulated + extrapolating recursion unless the
+point names another), a
 production run recorded in time blocks, the peak of C(Delta) = d<E_J>/dDelta
 with jackknife errors over the blocks, and at first-order temperatures the
 equal-height field and barrier of the reweighted P(e_Delta).  Every step runs
@@ -24,7 +25,8 @@ from .serve import delta_mid, tilted_weights
 
 _C = OBS_FIELDS.index("C_field")
 
-# (L, T, walkers, sweeps per iteration, iteration cap, production blocks, sweeps per block)
+# (L, T, walkers, sweeps per iteration, iteration cap, production blocks, sweeps per block
+#  [, weight recursion flags; default accumulated + extrapolating])
 POINTS = (
     (8, 1.0, 512, 1000, 1500, 8, 5000),
     (12, 1.0, 512, 2000, 1500, 8, 10000),
@@ -45,10 +47,14 @@ POINTS = (
     (16, 1.4182, 1024, 4000, 800, 8, 10000),
     (20, 1.4182, 1024, 4000, 800, 8, 10000),
 )
-# L=20 at T=0.9 is not in the list: from the tilted start the accumulated
-# recursion did not reach a flat histogram in 1500 iterations of 4000 sweeps
-# (the walkers stay on their side of a barrier of about exp(200)), and no
-# point of the production run is meaningful without it.
+# L=20 at T=0.9 is not in the list.  The accumulated recursion stalls there
+# (walkers trapped on either side of a barrier of about exp(200) reach no new
+# bin, so its statistics never restart and its steps shrink); extrapolation
+# alone reaches a flat histogram in 60-70 iterations, but two production runs
+# of 8 x 10^4 and 8 x 4 10^4 sweeps disagree on Delta* by 10-20 times their
+# jackknife errors: the walkers cross the barrier too rarely for runs of this
+# length.  A point with a recursion of its own is written
+# (20, 0.9, 1024, 8000, 600, 8, 40000, REC_EXTRAPOLATE).
 FIRST_ORDER_T = 1.4182  # below the tricritical temperature the transition is first order
 
 
@@ -79,13 +85,13 @@ def _bracket(grid: np.ndarray, values: np.ndarray):
 
 
 def run_point(L: int, T: float, walkers: int, sweeps: int, cap: int, n_blocks: int, block_sweeps: int,
-              seed: int = 0, grid=None, log=None) -> dict:
+              recursion: int = REC_ACCUMULATED | REC_EXTRAPOLATE, seed: int = 0, grid=None, log=None) -> dict:
     t0 = time.perf_counter()
     dm = delta_mid(T)
     grid = np.linspace(dm - 1.0, dm + 0.5, 301) if grid is None else np.asarray(grid, dtype=np.float64)
     job = MucaJob(L, T, walkers, seed=seed, lnW=tilted_weights(L, T), max_delta=len(grid))
-    job.set_recursion(REC_ACCUMULATED | REC_EXTRAPOLATE)
-    out = {"L": L, "T": T, "walkers": walkers, "sweeps_per_iteration": sweeps}
+    job.set_recursion(recursion)
+    out = {"L": L, "T": T, "walkers": walkers, "sweeps_per_iteration": sweeps, "recursion": recursion}
     out.update(converge(job, sweeps, cap, log=log))
     blocks, total = analysis.production_blocks(job, n_blocks, block_sweeps)
     out["production_sweeps"] = n_blocks * block_sweeps
