@@ -149,7 +149,10 @@ int muca_update_weights(muca_job *job, const int64_t *hist, double *lnW_out, dou
  *     weighted by its inverse Poisson variance H(E)H(E+1)/(H(E)+H(E+1)); a
  *     pair with one visited bin takes the plain step; lnW(0) is kept and the
  *     rest rebuilt from the differences.  The accumulated statistics restart
- *     whenever an iteration reaches a bin no earlier iteration did.
+ *     whenever an iteration reaches a bin no earlier iteration did.  When the
+ *     walkers stay trapped on either side of a strong first-order barrier, no
+ *     new bin is reached and the steps keep shrinking; such jobs converge
+ *     with MUCA_REC_EXTRAPOLATE alone or with the plain recursion.
  *   MUCA_REC_EXTRAPOLATE: bins outside the range visited in any iteration so
  *     far continue the mean slope of the last min(8, width) differences inside
  *     it, at each end.
