@@ -1,6 +1,7 @@
-"""The small-L campaign driver end to end on a tiny point: converged weights,
+"""The small-L campaign driver end to end: on a tiny point, converged weights,
 a peak of C(Delta) inside the scanned range with jackknife errors, and the
-equal-height field at a first-order temperature."""
+equal-height field at a first-order temperature; on small first-order points,
+the paper's transition fields and volume scaling."""
 import math
 import sys
 
@@ -25,3 +26,25 @@ def test_campaign_point_l4():
     if "delta_eqh" in out:
         assert abs(out["delta_eqh"] - out["delta_star"]) < 0.5
         assert np.isfinite(out["barrier"])
+
+
+def test_first_order_fields_match_the_paper():
+    """The whole pipeline (weight iteration, production, reweighting, peak
+    search) against numbers the paper prints.  Below the tricritical point the
+    pseudo-transition field moves little with L, so already at L = 8 and 12
+    it must lie inside the paper's error bars: Delta*(T=1) = 2.944(5) and
+    Delta*(T=0.9) = 2.964(6) (Sec. III); the equal-height field must agree
+    with it; and the peak per site must grow with the volume, C*/V ~ L^p with
+    the paper's p = 3.00(2)."""
+    res = {}
+    for (L, T) in ((8, 1.0), (12, 1.0), (12, 0.9)):
+        print(f"[campaign] L={L} T={T} against the paper", flush=True)
+        pt = [p for p in campaign.POINTS if p[:2] == (L, T)][0]
+        res[(L, T)] = out = campaign.run_point(*pt)
+        assert out["flat"] and "delta_star" in out and "delta_eqh" in out, out
+        assert abs(out["delta_eqh"] - out["delta_star"]) < 5e-4, out
+    assert abs(res[(8, 1.0)]["delta_star"] - 2.944) < 0.005
+    assert abs(res[(12, 1.0)]["delta_star"] - 2.944) < 0.005
+    assert abs(res[(12, 0.9)]["delta_star"] - 2.964) < 0.006
+    p = math.log((res[(12, 1.0)]["C_star"] / 12 ** 3) / (res[(8, 1.0)]["C_star"] / 8 ** 3)) / math.log(12 / 8)
+    assert abs(p - 3.00) < 0.02 * 3, p
