@@ -192,6 +192,14 @@ int muca_reweight_sums(muca_job *job, const int64_t *sums, const uint64_t *sm4, 
  * device block.  MUCA_E_STATE when nothing has been recorded.  Synchronises. */
 int muca_reweight_hist(muca_job *job, double delta, double *lnP_out);
 
+/* Reweighted distribution of E_Delta as muca_reweight_hist, from a
+ * caller-supplied histogram hist (V+1 non-negative int64, e.g. the production
+ * histogram with one time block left out, for jackknife errors of the
+ * equal-height field, Sec. II-III) recorded under the job's current weights.
+ * MUCA_E_INVAL on a negative entry, MUCA_E_STATE if hist holds no entry.
+ * Uses the job's obs buffer as staging.  Synchronises. */
+int muca_reweight_hist_sums(muca_job *job, const int64_t *hist, double delta, double *lnP_out);
+
 /* Copy walker state to the host: spins (n_walkers x V int8, site-indexed
  * i = x + L(y + Lz), may be NULL) and state (n_walkers x 4 int64: E_J, E_Delta,
  * M, sweeps done; may be NULL).  Synchronises. */

@@ -90,10 +90,16 @@ def _peaks(lnP: np.ndarray, split: int):
     return a, float(lnP[a]), b, float(lnP[b])
 
 
-def equal_height(job: MucaJob, lo: float, hi: float, split: int, tol: float = 1e-11) -> Tuple[float, float]:
-    """(Delta_eqh, barrier) with Delta_eqh in [lo, hi]."""
+def _log_hist(job: MucaJob, hist, d: float) -> np.ndarray:
+    return job.reweight_hist(d) if hist is None else job.reweight_hist_sums(hist, d)
+
+
+def equal_height(job: MucaJob, lo: float, hi: float, split: int, tol: float = 1e-11,
+                 hist=None) -> Tuple[float, float]:
+    """(Delta_eqh, barrier) with Delta_eqh in [lo, hi], from the production
+    histogram or, when given, from hist (V+1 counts under the job's weights)."""
     def diff(d):
-        _, a, _, b = _peaks(job.reweight_hist(d), split)
+        _, a, _, b = _peaks(_log_hist(job, hist, d), split)
         return b - a
     if not (diff(lo) > 0 and diff(hi) < 0):
         raise ValueError("peak heights do not cross on the bracket")
@@ -104,8 +110,22 @@ def equal_height(job: MucaJob, lo: float, hi: float, split: int, tol: float = 1e
         else:
             hi = mid
     d = 0.5 * (lo + hi)
-    lnP = job.reweight_hist(d)
+    lnP = _log_hist(job, hist, d)
     e1, p1, e2, p2 = _peaks(lnP, split)
     pmin = float(np.min(lnP[e1:e2 + 1]))
     barrier = (max(p1, p2) - pmin) / (2.0 * job.beta * d) if job.beta > 0 and d != 0 else float("nan")
     return d, barrier
+
+
+def jackknife_equal_height(job: MucaJob, blocks: List[dict], total: dict, lo: float, hi: float, split: int,
+                           tol: float = 1e-11):
+    """Delta_eqh and the barrier on all measurements, with jackknife errors
+    over the production blocks (each leave-one-out histogram reweighted on
+    the device)."""
+    d, b = equal_height(job, lo, hi, split, tol, hist=total["H"])
+    loo = [equal_height(job, lo, hi, split, tol, hist=[x - y for x, y in zip(total["H"], blk["H"])])
+           for blk in blocks]
+    dj, de = jackknife([x[0] for x in loo])
+    bj, be = jackknife([x[1] for x in loo])
+    return {"delta_eqh": d, "barrier": b, "delta_eqh_err": de, "barrier_err": be,
+            "delta_eqh_jk_mean": dj, "barrier_jk_mean": bj, "blocks": len(blocks)}

@@ -647,6 +647,31 @@ int muca_reweight_hist(muca_job *j, double delta, double *lnP_out)
     return MUCA_OK;
 }
 
+int muca_reweight_hist_sums(muca_job *j, const int64_t *hist, double delta, double *lnP_out)
+{
+    if (!j || !hist || !lnP_out || !std::isfinite(delta)) return MUCA_E_INVAL;
+    const Layout &g = j->g;
+    int64_t n = 0;
+    for (int E = 0; E <= g.V; ++E) {
+        if (hist[E] < 0) return MUCA_E_INVAL;
+        n += hist[E];
+    }
+    if (n == 0) return MUCA_E_STATE;
+    if (int rc = use_device(j)) return rc;
+    unsigned char *scratch = reinterpret_cast<unsigned char *>(j->d.obs) + g.off_obs_sums;
+    HIP_TRY(hipMemcpyAsync(scratch, hist, sizeof(int64_t) * (g.V + 1), hipMemcpyHostToDevice, j->stream));
+    LogHistArgs a;
+    a.hist = reinterpret_cast<const unsigned long long *>(scratch);
+    a.lnw = reinterpret_cast<const double *>(reinterpret_cast<unsigned char *>(j->d.tables) + g.off_lnw);
+    a.lnp = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(j->d.obs) + g.off_obs_lnp);
+    a.V = g.V;
+    a.bd = j->beta * delta;
+    HIP_TRY(launch_log_hist(a, j->stream));
+    HIP_TRY(hipMemcpyAsync(lnP_out, a.lnp, sizeof(double) * (g.V + 1), hipMemcpyDeviceToHost, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    return MUCA_OK;
+}
+
 int muca_read_state(muca_job *j, int8_t *spins, int64_t *state)
 {
     if (!j) return MUCA_E_INVAL;

@@ -30,7 +30,7 @@ EXPORTS = (
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
     "muca_batch_set_launch", "muca_batch_get_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
-    "muca_reweight_hist", "muca_set_recursion",
+    "muca_reweight_hist", "muca_reweight_hist_sums", "muca_set_recursion",
 )
 
 # weight recursion flags (muca_set_recursion)
@@ -101,6 +101,7 @@ def lib():
     L.muca_flatness.argtypes = [P(i64), i32, i32, P(dbl)]
     L.muca_reweight_sums.argtypes = [vp, P(i64), P(ctypes.c_uint64), P(dbl), i32, P(dbl)]
     L.muca_reweight_hist.argtypes = [vp, dbl, P(dbl)]
+    L.muca_reweight_hist_sums.argtypes = [vp, P(i64), dbl, P(dbl)]
     for name in EXPORTS:
         if name not in ("muca_strerror", "muca_free", "muca_batch_free"):
             getattr(L, name).restype = ctypes.c_int
@@ -233,6 +234,15 @@ class MucaJob:
         """ln P(E_Delta) at Delta from the production histogram."""
         out = np.zeros(self.V + 1)
         _check(lib().muca_reweight_hist(self._h, float(delta), _p(out, ctypes.c_double)), "muca_reweight_hist")
+        return out
+
+    def reweight_hist_sums(self, hist, delta: float) -> np.ndarray:
+        """ln P(E_Delta) at Delta from a caller-supplied histogram (V+1 counts)."""
+        h = np.ascontiguousarray(hist, dtype=np.int64)
+        assert h.shape == (self.V + 1,)
+        out = np.zeros(self.V + 1)
+        _check(lib().muca_reweight_hist_sums(self._h, _p(h, ctypes.c_int64), float(delta), _p(out, ctypes.c_double)),
+               "muca_reweight_hist_sums")
         return out
 
     # -- weights, state, accumulators ---------------------------------------

@@ -89,3 +89,78 @@ def test_log_hist_and_equal_height_match_oracle():
     assert abs(d_g - d_o) < 1e-9
     assert abs(b_g - b_o) < 1e-9 * max(1.0, abs(b_o))
     job.free()
+
+
+def test_equal_height_closed_form_on_device():
+    """The device reweighting of a histogram whose reweighted distribution is
+    known in closed form (Sec. II): H(E) integer counts recorded under weights
+    lnW(E) = ln H(E) - g(E) - beta D0 E, g the symmetric quartic double well
+    -a((E - c)^2 - s^2)^2 / s^4 about c = V/2 with peaks at c +- s.  Then
+    ln P(E; Delta) = g(E) - beta (Delta - D0) E + const, so the two peaks are
+    equal at D0 and the barrier of Sec. III is a / (2 beta D0), independently of
+    the oracle's code."""
+    L, T, D0, a, s = 4, 0.9, 2.964, 7.5, 12
+    V, beta = L ** 3, 1.0 / 0.9
+    print(f"[analysis] closed-form equal height L={L} T={T}", flush=True)
+    E = np.arange(V + 1, dtype=np.float64)
+    g = -a * ((E - V / 2) ** 2 - s * s) ** 2 / s ** 4
+    rng = np.random.default_rng(11)
+    H = rng.integers(10 ** 9, 10 ** 12, size=V + 1).astype(np.int64)
+    lnW = np.log(H.astype(np.float64)) - g - beta * D0 * E
+    job = MucaJob(L, T, 1, seed=0, lnW=lnW, max_delta=1)
+    d, b = analysis.equal_height(job, D0 - 0.05, D0 + 0.05, V // 2, hist=H)
+    assert abs(d - D0) < 1e-9
+    assert abs(b - a / (2.0 * beta * D0)) < 1e-9 * a / (2.0 * beta * D0)
+    lnP = job.reweight_hist_sums(H, D0)
+    assert np.all(np.abs((lnP - lnP.max()) - g) < 1e-9 * np.maximum(1.0, np.abs(g)))
+    job.free()
+
+
+@pytest.mark.parametrize("T", [1.0, 1.6])
+def test_peak_on_device_matches_exact_l2(T):
+    """Delta* (the maximum of C(Delta), Sec. III) from the device reweighting of
+    the exact L = 2 expected per-bin sums (scaled to 10^12 measurements and
+    rounded to integers) against the enumeration: at Delta* the exact
+    dC/dDelta vanishes and C* equals the exact C there."""
+    from tests import l2_exact
+
+    beta = 1.0 / T
+    lnW = -l2_exact.ln_g_beta(beta)
+    ex = l2_exact.muca_bin_sums(beta, lnW, n=1e12)
+    sums = {k: [int(round(v)) for v in ex[k]] for k in ("H", "SJ", "SJJ", "SA", "SM2", "SM4")} | {"V": 8}
+    job = MucaJob(2, T, 1, seed=0, lnW=lnW, max_delta=1)
+    d, c = analysis.peak(job, 2.0, 4.0, sums=sums)
+    exact = l2_exact.canonical(beta, d)
+    assert abs(exact["dC_dDelta"]) < 1e-8 * max(1.0, abs(exact["C_field"]))
+    assert abs(c - exact["C_field"]) < 1e-9 * abs(exact["C_field"])
+    job.free()
+
+
+def test_jackknife_equal_height_matches_oracle():
+    """Jackknife of the equal-height field and barrier over production blocks:
+    every leave-one-out histogram reweighted on the device, against the
+    oracle's reweighting of the same (bit-identical) blocks."""
+    L, T = 4, 1.0
+    print(f"[analysis] jackknife equal height L={L} T={T}", flush=True)
+    job, o = make_pair(L, T, 16, 23, 10, 1000, lnW=-(1.0 / T) * 2.944 * np.arange(L ** 3 + 1))
+    blocks, total = analysis.production_blocks(job, 4, 1500)
+    oblocks, ototal = oracle_blocks(o, 4, 1500)
+    assert total == ototal and blocks == oblocks
+    split = o.V // 2
+    grid = np.linspace(2.0, 4.0, 81)
+    diffs = []
+    for d in grid:
+        _, a, _, b = oracle.two_peaks(oracle.reweighted_log_hist(o.V, o.beta, o.lnW, ototal["H"], d), split)
+        diffs.append(b - a)
+    k = next(i for i in range(len(grid) - 1) if diffs[i] > 0 and diffs[i + 1] < 0)
+    lo, hi = grid[max(k - 1, 0)], grid[min(k + 2, len(grid) - 1)]
+    jk = analysis.jackknife_equal_height(job, blocks, total, lo, hi, split)
+    loo = [oracle.equal_height(o.V, o.beta, o.lnW, [x - y for x, y in zip(ototal["H"], b["H"])], lo, hi, split)
+           for b in oblocks]
+    d_o, b_o = oracle.equal_height(o.V, o.beta, o.lnW, ototal["H"], lo, hi, split)
+    assert abs(jk["delta_eqh"] - d_o) < 1e-9 and abs(jk["barrier"] - b_o) < 1e-9 * max(1.0, b_o)
+    de = oracle.jackknife([x[0] for x in loo])[1]
+    be = oracle.jackknife([x[1] for x in loo])[1]
+    assert abs(jk["delta_eqh_err"] - de) < 1e-6 * max(de, 1e-6)
+    assert abs(jk["barrier_err"] - be) < 1e-6 * max(be, 1e-6)
+    job.free()

@@ -434,3 +434,92 @@ def test_jackknife_of_a_linear_statistic_is_the_standard_error():
     m, e = oracle.jackknife(loo)
     assert abs(m - x.mean()) < 1e-12
     assert abs(e - x.std(ddof=1) / math.sqrt(20)) < 1e-12
+
+
+def _double_well(V, beta, D0, a, s, lnW):
+    """A synthetic sample whose reweighted distribution is known in closed form.
+
+    With H(E) = exp(g(E) + beta D0 E + lnW(E)) recorded under weights lnW, the
+    reweighted distribution at Delta is ln P(E) = g(E) - beta (Delta - D0) E + const
+    (Sec. II: each entry of bin E carries exp(-beta Delta E) / W(E)).  g is the
+    symmetric quartic double well -a ((E - c)^2 - s^2)^2 / s^4 about c = V/2,
+    with maxima g = 0 at c +- s and g(c) = -a: the two peaks are equal exactly at
+    Delta = D0, and ln(P_max / P_min) there is a, P_min taken between the peaks.
+    Outside the peaks g falls far below -a."""
+    E = np.arange(V + 1, dtype=np.float64)
+    c = V / 2
+    g = -a * ((E - c) ** 2 - s * s) ** 2 / s ** 4
+    return np.exp(g + beta * D0 * E + lnW)
+
+
+@pytest.mark.parametrize("T,D0,a", [(0.9, 2.964, 7.5), (1.0, 2.944, 3.0), (2.0, 2.523, 11.0)])
+def test_equal_height_and_barrier_closed_form(T, D0, a):
+    """Sec. III: the barrier is B = ln(P_max / P_min) / (2 beta Delta) at the
+    equal-height field.  On the closed-form double well, Delta_eqh = D0 and
+    B = a / (2 beta D0); a wrong normalisation, sign of the weights or range of
+    P_min fails."""
+    beta = 1.0 / T
+    V, s = 60, 12
+    lnW = np.random.default_rng(7).normal(0.0, 2.0, size=V + 1) - 0.4 * beta * D0 * np.arange(V + 1)
+    H = _double_well(V, beta, D0, a, s, lnW)
+    d, barrier = oracle.equal_height(V, beta, lnW, list(H), D0 - 0.05, D0 + 0.05, split=V // 2)
+    assert abs(d - D0) < 1e-9
+    assert abs(barrier - a / (2.0 * beta * D0)) < 1e-9 * (a / (2.0 * beta * D0))
+    lnP = oracle.reweighted_log_hist(V, beta, lnW, list(H), D0)
+    assert int(np.argmax(lnP[: V // 2])) == V // 2 - s and int(np.argmax(lnP[V // 2:])) == s
+
+
+def _exact_l2_log_hist(beta, delta):
+    """ln P(E_Delta) at (beta, Delta) on L = 2, summed over all 3^8 states."""
+    a = -beta * (l2_exact.EJ + delta * l2_exact.ED)
+    w = np.exp(a - a.max())
+    P = np.array([w[l2_exact.ED == E].sum() for E in range(9)])
+    return np.log(P / P.sum())
+
+
+@pytest.mark.parametrize("T", [0.25, 0.5, 1.0])
+def test_barrier_exact_l2(T):
+    """The equal-height field and the barrier of Sec. III on L = 2 against the
+    enumeration: the field where the maxima of P(E_Delta) below and above
+    E_Delta = 4 are equal (found here by bisection on the exact distribution),
+    and ln(P_max / P_min) / (2 beta Delta) with P_min between the peaks."""
+    beta = 1.0 / T
+    lnW = -l2_exact.ln_g_beta(beta)
+    sums = l2_exact.muca_bin_sums(beta, lnW, n=1.0)
+    d_o, b_o = oracle.equal_height(8, beta, lnW, sums["H"], 2.5, 3.5, split=4)
+    lo, hi = 2.5, 3.5
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        p = _exact_l2_log_hist(beta, mid)
+        if p[4:].max() > p[:4].max():
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo < 1e-13:
+            break
+    d_x = 0.5 * (lo + hi)
+    p = _exact_l2_log_hist(beta, d_x)
+    e1, e2 = int(np.argmax(p[:4])), 4 + int(np.argmax(p[4:]))
+    b_x = (max(p[e1], p[e2]) - p[e1:e2 + 1].min()) / (2.0 * beta * d_x)
+    assert abs(d_o - d_x) < 1e-9
+    assert abs(b_o - b_x) < 1e-9 * max(1.0, abs(b_x))
+
+
+def test_sum_of_m4_carries_past_64_bits():
+    """The per-bin sum of M^4 is kept in 128 bits (Sec. II reweighting of <M^4>).
+    A frozen ordered lattice (L = 30, all spins +1, T = 0.05: every move costs at
+    least exp(-120), so only u31 = 0 would accept) records M = V after every
+    sweep: the sum is exactly n V^4, past 2^64 several times over."""
+    L, T, nw, sweeps = 30, 0.05, 4, 48
+    V = L ** 3
+    job = oracle.OracleJob(L, T, nw, seed=77)
+    job.spins[:] = 1
+    job.state[:] = [-3 * V, V, V, 0]
+    job.sweep(sweeps, record=True)
+    assert np.all(job.spins == 1) and np.all(job.state[:, :3] == [-3 * V, V, V])
+    n = nw * sweeps
+    s = job.bin_sums()
+    assert s["H"][V] == n and sum(s["H"]) == n
+    assert s["SM4"][V] == n * V ** 4 and (n * V ** 4) >> 64 == 5
+    assert s["SM2"][V] == n * V * V and s["SA"][V] == n * V and s["SJ"][V] == -3 * V * n
+    assert int(job.sm4_hi[V]) == 5 and int(job.sm4_lo[V]) == (n * V ** 4) & (2 ** 64 - 1)
