@@ -289,6 +289,27 @@ int muca_batch_sweep(muca_batch *batch, int64_t n_sweeps, uint32_t flags);
 /* Release the batch's host resources (waits for queued work).  NULL ignored. */
 void muca_batch_free(muca_batch *batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the batched
+ * sweep of muca_batch_create + muca_batch_sweep in one call, in the default
+ * launch shape of muca_batch_create, with the job table, the work list and the
+ * work counter in a static device array owned by the library instead of a
+ * caller buffer.  The array holds MUCA_STATIC_MAX_JOBS jobs and
+ * MUCA_STATIC_MAX_TILES tiles (a tile is the walkers of one block: 4 walkers of
+ * one job at one wave each, or 2 or 1 when 4 lattices do not fit in LDS), so
+ * at least 65536 walkers: 540 KiB per device, held until the process ends.  Its device address is taken once per device when the first job is
+ * created there (muca_init).  jobs: n_jobs distinct jobs created on one device
+ * with one stream; n_sweeps and flags as for muca_batch_sweep, with the same
+ * results.  The call allocates nothing; it copies the job table from host
+ * memory the library owns and waits for the previous call's copy first.
+ * Every call on a device shares that device's array and rewrites it: calls
+ * that overlap on one device (two streams, or two threads) race.
+ * MUCA_E_SIZE beyond the limits, MUCA_E_INVAL on a bad list, MUCA_E_DEVICE if
+ * the array's address could not be taken.  Asynchronous on the jobs' stream. */
+#define MUCA_STATIC_MAX_JOBS 256
+#define MUCA_STATIC_MAX_TILES 65536
+int muca_batch_sweep_static(muca_job *const *jobs, int32_t n_jobs, int64_t n_sweeps, uint32_t flags);
+
 /* Host-only: flatness min / mean of hist[lo..hi] (inclusive bins, 0 <= lo <= hi),
  * the convergence measure of the weight iteration restricted to a window of
  * E_Delta; 0 when the window holds no entries. */

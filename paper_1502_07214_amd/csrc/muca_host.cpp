@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -76,6 +77,8 @@ bool params_ok(const muca_params *p)
 }
 
 double beta_of(double T) { return std::isinf(T) ? 0.0 : 1.0 / T; }
+
+void static_scratch_setup(int device);
 
 Layout make_layout(const muca_params *p)
 {
@@ -342,6 +345,7 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
     };
     if (hipGetDevice(&j->device) != hipSuccess) return bail(fail_device(hipGetLastError(), "hipGetDevice"));
     j->max_lds = query_max_lds(j->device);
+    static_scratch_setup(j->device);
     if (hipDeviceGetAttribute(&j->n_cu, hipDeviceAttributeMultiprocessorCount, j->device) != hipSuccess)
         j->n_cu = 256;
     hipError_t e;
@@ -842,21 +846,142 @@ size_t batch_bytes(size_t n_jobs, size_t walkers)
     return align_up(n_jobs * sizeof(BatchJob), 256) + align_up(walkers * sizeof(int2), 256) + 256;
 }
 
-int tile_wpw(const muca_batch *b, int wpw, size_t k) { return wpw ? wpw : b->job_wpw[k]; }
+// The jobs of one batched launch and the waves per walker of their tiles.
+struct BatchPlan {
+    muca_job *const *jobs;
+    int n;
+    int wpw;             // 1, 2 or 4 for every job, or 0: job_wpw[k] for job k
+    const int *job_wpw;  // n entries when wpw == 0
+    size_t tab_bytes;    // LDS reserved for staged tables (0: none)
+    int wpw_of(int k) const { return wpw ? wpw : job_wpw[k]; }
+};
 
-// Tiles of 4/wpw consecutive walkers of one job, jobs with the most work per
-// walker (largest V) first.
-int build_tiles(muca_batch *b, int wpw, std::vector<int2> &tiles)
+// LDS of a block: the fixed part and the lattice slots of the largest tile.
+size_t plan_lds(const BatchPlan &p)
 {
-    std::vector<int> idx(b->jobs.size());
-    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return b->jobs[x]->g.V > b->jobs[y]->g.V; });
-    tiles.clear();
-    for (int jx : idx) {
-        const int wpb = 4 / tile_wpw(b, wpw, (size_t)jx);
-        for (int w = 0; w < b->jobs[jx]->g.n_walkers; w += wpb) tiles.push_back(make_int2(jx, w));
+    size_t lat = 0;
+    for (int k = 0; k < p.n; ++k) lat = std::max(lat, (size_t)(4 / p.wpw_of(k)) * (size_t)p.jobs[k]->g.Vp);
+    return kLdsFixed + align_up(lat, 16);
+}
+
+// LDS a job's thresholds and neighbour table take when staged.
+size_t job_tab_bytes(const muca_job *j)
+{
+    return align_up(16 * ((size_t)j->g.V + 1 + 2 * kRPad), 16) + align_up((size_t)12 * j->g.Vp, 16);
+}
+
+// Per-block LDS up to which a batch stages tables: enough for the thresholds
+// of served-size jobs while four blocks still fit on a CU.
+constexpr size_t kBatchLdsBudget = 40 * 1024;
+
+// The largest staged-table size that keeps the block within the budget.
+size_t plan_tab_bytes(const BatchPlan &p)
+{
+    const size_t base = plan_lds(p);
+    size_t best = 0;
+    for (int k = 0; k < p.n; ++k) {
+        const size_t t = job_tab_bytes(p.jobs[k]);
+        if (base + t <= kBatchLdsBudget) best = std::max(best, t);
     }
-    return (int)tiles.size();
+    return best;
+}
+
+// order[0..n): job indices with the most work per walker (largest V) first,
+// equal V in the order given (a stable insertion sort: no allocation).
+void heaviest_first(muca_job *const *jobs, int n, int *order)
+{
+    for (int k = 0; k < n; ++k) {
+        int m = k;
+        while (m > 0 && jobs[order[m - 1]]->g.V < jobs[k]->g.V) {
+            order[m] = order[m - 1];
+            --m;
+        }
+        order[m] = k;
+    }
+}
+
+// Tiles of the plan: 4/wpw consecutive walkers of one job each.
+int count_tiles(const BatchPlan &p)
+{
+    int t = 0;
+    for (int k = 0; k < p.n; ++k) {
+        const int wpb = 4 / p.wpw_of(k);
+        t += (p.jobs[k]->g.n_walkers + wpb - 1) / wpb;
+    }
+    return t;
+}
+
+// Host images of the device job table (n entries) and of the tile list
+// (count_tiles(p) entries, jobs in `order`); returns the number of tiles.
+int fill_batch(const BatchPlan &p, const int *order, BatchJob *bj, int2 *tiles)
+{
+    for (int k = 0; k < p.n; ++k) {
+        const muca_job *j = p.jobs[k];
+        const Layout &g = j->g;
+        unsigned char *dt = reinterpret_cast<unsigned char *>(j->d.tables);
+        BatchJob &J = bj[k];
+        J.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
+        J.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
+        J.hist = reinterpret_cast<unsigned long long *>(j->d.hist);
+        J.bp = reinterpret_cast<const double *>(dt + g.off_bp);
+        J.r = reinterpret_cast<const double *>(dt + g.off_r);
+        J.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
+        J.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
+        J.err = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256));
+        J.V = g.V;
+        J.Vp = g.Vp;
+        J.n_walkers = g.n_walkers;
+        J.n_classes = g.C;
+        for (int c = 0; c <= kMaxClasses; ++c) J.cls[c] = g.cls[c];
+        J.k0 = j->k0;
+        J.k1 = j->k1;
+        J.lds_tables = p.tab_bytes > 0 && job_tab_bytes(j) <= p.tab_bytes ? 1 : 0;
+        J.wpw = p.wpw_of(k);
+    }
+    int t = 0;
+    for (int m = 0; m < p.n; ++m) {
+        const int jx = order[m];
+        const int wpb = 4 / p.wpw_of(jx);
+        for (int w = 0; w < p.jobs[jx]->g.n_walkers; w += wpb) tiles[t++] = make_int2(jx, w);
+    }
+    return t;
+}
+
+// The enqueue common to both batched entry points: for each chunk of at most
+// kMaxSweepsPerLaunch sweeps, clear the work counter (a fill kernel) and launch.
+int enqueue_batch(const BatchPlan &p, int bpl, int blocks, const BatchJob *d_jobs, const int2 *d_tiles, int n_tiles,
+                  unsigned *d_counter, int64_t n_sweeps, bool record, hipStream_t stream)
+{
+    BatchArgs a;
+    a.jobs = d_jobs;
+    a.tiles = d_tiles;
+    a.n_tiles = n_tiles;
+    a.counter = d_counter;
+    a.lds_off_lat = kLdsFixed;
+    a.lds_off_tab = (int)plan_lds(p);
+    const size_t lds = plan_lds(p) + p.tab_bytes;
+    int64_t left = n_sweeps;
+    while (left > 0) {
+        const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
+        a.n_sweeps = chunk;
+        HIP_TRY(launch_zero(d_counter, 16, stream));
+        HIP_TRY(launch_batch(a, p.wpw, bpl, record, lds, blocks, stream));
+        left -= chunk;
+    }
+    if (record)
+        for (int k = 0; k < p.n; ++k) p.jobs[k]->recorded += n_sweeps;
+    return MUCA_OK;
+}
+
+BatchPlan plan_of(const muca_batch *b, int wpw)
+{
+    BatchPlan p;
+    p.jobs = b->jobs.data();
+    p.n = (int)b->jobs.size();
+    p.wpw = wpw;
+    p.job_wpw = b->job_wpw.data();
+    p.tab_bytes = b->tab_bytes;
+    return p;
 }
 
 // Waves per walker of each job in a launch that mixes them (an opt-in shape:
@@ -885,10 +1010,9 @@ void choose_job_wpw(muca_batch *b)
     const muca_job *j0 = b->jobs[0];
     const long simds = 4L * (j0->n_cu > 0 ? j0->n_cu : 256);
     b->job_wpw.assign(b->jobs.size(), 1);
-    std::vector<size_t> idx(b->jobs.size());
-    for (size_t k = 0; k < idx.size(); ++k) idx[k] = k;
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return b->jobs[x]->g.V > b->jobs[y]->g.V; });
-    for (size_t k : idx) {
+    std::vector<int> idx(b->jobs.size());
+    heaviest_first(b->jobs.data(), (int)b->jobs.size(), idx.data());
+    for (int k : idx) {
         const Layout &g = b->jobs[k]->g;
         const bool fills = g.V / g.C >= 4 * 64 * 4;
         const long extra = 3L * g.n_walkers;
@@ -901,36 +1025,14 @@ void choose_job_wpw(muca_batch *b)
         if (kLdsFixed + align_up((size_t)4 * b->jobs[k]->g.Vp, 16) > (size_t)j0->max_lds) b->job_wpw[k] = 4;
 }
 
-size_t job_tab_bytes(const muca_job *j);
-
 int upload_batch(muca_batch *b)
 {
-    std::vector<int2> tiles;
-    b->n_tiles = build_tiles(b, b->wpw, tiles);
+    const BatchPlan p = plan_of(b, b->wpw);
+    std::vector<int> order(b->jobs.size());
+    heaviest_first(p.jobs, p.n, order.data());
     std::vector<BatchJob> bj(b->jobs.size());
-    for (size_t k = 0; k < b->jobs.size(); ++k) {
-        const muca_job *j = b->jobs[k];
-        const Layout &g = j->g;
-        unsigned char *dt = reinterpret_cast<unsigned char *>(j->d.tables);
-        BatchJob &J = bj[k];
-        J.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
-        J.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
-        J.hist = reinterpret_cast<unsigned long long *>(j->d.hist);
-        J.bp = reinterpret_cast<const double *>(dt + g.off_bp);
-        J.r = reinterpret_cast<const double *>(dt + g.off_r);
-        J.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
-        J.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
-        J.err = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256));
-        J.V = g.V;
-        J.Vp = g.Vp;
-        J.n_walkers = g.n_walkers;
-        J.n_classes = g.C;
-        for (int c = 0; c <= kMaxClasses; ++c) J.cls[c] = g.cls[c];
-        J.k0 = j->k0;
-        J.k1 = j->k1;
-        J.lds_tables = b->tab_bytes > 0 && job_tab_bytes(j) <= b->tab_bytes ? 1 : 0;
-        J.wpw = tile_wpw(b, b->wpw, k);
-    }
+    std::vector<int2> tiles((size_t)count_tiles(p));
+    b->n_tiles = fill_batch(p, order.data(), bj.data(), tiles.data());
     const size_t off_tiles = align_up(bj.size() * sizeof(BatchJob), 256);
     HIP_TRY(hipMemcpyAsync(b->dev, bj.data(), bj.size() * sizeof(BatchJob), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->dev + off_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice,
@@ -939,35 +1041,75 @@ int upload_batch(muca_batch *b)
     return MUCA_OK;
 }
 
-// LDS of a block: the fixed part and the lattice slots of the largest tile.
-size_t batch_lds(const muca_batch *b, int wpw)
+// Common checks of a job list: non-null, distinct, one device and one stream.
+int check_job_list(muca_job *const *jobs, int32_t n_jobs)
 {
-    size_t lat = 0;
-    for (size_t k = 0; k < b->jobs.size(); ++k)
-        lat = std::max(lat, (size_t)(4 / tile_wpw(b, wpw, k)) * (size_t)b->jobs[k]->g.Vp);
-    return kLdsFixed + align_up(lat, 16);
-}
-
-// LDS a job's thresholds and neighbour table take when staged.
-size_t job_tab_bytes(const muca_job *j)
-{
-    return align_up(16 * ((size_t)j->g.V + 1 + 2 * kRPad), 16) + align_up((size_t)12 * j->g.Vp, 16);
-}
-
-// Per-block LDS up to which a batch stages tables: enough for the thresholds
-// of served-size jobs while four blocks still fit on a CU.
-constexpr size_t kBatchLdsBudget = 40 * 1024;
-
-// The largest staged-table size that keeps the block within the budget.
-size_t choose_tab_bytes(const muca_batch *b, int wpw)
-{
-    const size_t base = batch_lds(b, wpw);
-    size_t best = 0;
-    for (const muca_job *j : b->jobs) {
-        const size_t t = job_tab_bytes(j);
-        if (base + t <= kBatchLdsBudget) best = std::max(best, t);
+    if (!jobs || n_jobs < 1) return MUCA_E_INVAL;
+    for (int k = 0; k < n_jobs; ++k) {
+        if (!jobs[k]) return MUCA_E_INVAL;
+        if (jobs[k]->stream != jobs[0]->stream || jobs[k]->device != jobs[0]->device) return MUCA_E_INVAL;
+        for (int m = 0; m < k; ++m)
+            if (jobs[m] == jobs[k]) return MUCA_E_INVAL;
     }
-    return best;
+    return MUCA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of muca_batch_sweep_static: the job table, the work list and
+// the work counter of a batched launch, in a file-scope device array (one copy
+// per device, held until the process ends).  In host code `scratch` names a
+// host-side stand-in: its device address on each device comes from
+// hipGetSymbolAddress, taken once per device when the first job is created
+// there (static_scratch_setup), and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+constexpr int kStaticMaxJobs = MUCA_STATIC_MAX_JOBS;
+constexpr int kStaticMaxTiles = MUCA_STATIC_MAX_TILES;
+constexpr size_t kStaticOffTiles = (kStaticMaxJobs * sizeof(BatchJob) + 255) / 256 * 256;
+constexpr size_t kStaticOffCounter = kStaticOffTiles + (size_t)kStaticMaxTiles * sizeof(int2);
+constexpr size_t kStaticScratchBytes = kStaticOffCounter + 256;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+struct StaticScratch {
+    unsigned char *dev = nullptr;  // device address of `scratch` on this device
+    hipEvent_t staged = nullptr;   // recorded after the last upload from the host images below
+    std::mutex lock;               // host images are shared by the calls on this device
+    BatchJob host_jobs[kStaticMaxJobs];
+    int2 host_tiles[kStaticMaxTiles];
+    int order[kStaticMaxJobs];
+};
+
+std::mutex g_static_lock;
+StaticScratch *g_static[kMaxDevices] = {};
+hipError_t g_static_error[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of the
+// scratch array and the event that guards the host images.  A failure is kept
+// and reported by muca_batch_sweep_static; it does not fail job creation.
+void static_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> guard(g_static_lock);
+    if (g_static[device] || g_static_error[device] != hipSuccess) return;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        g_static_error[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        return;
+    }
+    StaticScratch *st = new (std::nothrow) StaticScratch();
+    if (!st) {
+        g_static_error[device] = hipErrorOutOfMemory;
+        return;
+    }
+    if ((e = hipEventCreateWithFlags(&st->staged, hipEventDisableTiming)) != hipSuccess) {
+        delete st;
+        g_static_error[device] = e;
+        return;
+    }
+    st->dev = reinterpret_cast<unsigned char *>(ptr);
+    g_static[device] = st;
 }
 
 }  // namespace
@@ -994,11 +1136,7 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
     if (int rc = muca_batch_query_size(jobs, n_jobs, &need)) return rc;
     if (!dev_buffer || (reinterpret_cast<uintptr_t>(dev_buffer) & 255u)) return MUCA_E_INVAL;
     if (bytes < need) return MUCA_E_SIZE;
-    for (int k = 0; k < n_jobs; ++k) {
-        if (jobs[k]->stream != jobs[0]->stream || jobs[k]->device != jobs[0]->device) return MUCA_E_INVAL;
-        for (int m = 0; m < k; ++m)
-            if (jobs[m] == jobs[k]) return MUCA_E_INVAL;
-    }
+    if (int rc = check_job_list(jobs, n_jobs)) return rc;
     muca_batch *b = new (std::nothrow) muca_batch();
     if (!b) return MUCA_E_SIZE;
     b->jobs.assign(jobs, jobs + n_jobs);
@@ -1013,10 +1151,11 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
     b->wpw = 1;
     b->bpl = 1;
     b->blocks = 0;
+    b->tab_bytes = 0;
     choose_job_wpw(b);  // the shape of a per-job launch, if a caller asks for one
     const int max_lds = jobs[0]->max_lds;
-    while (batch_lds(b, b->wpw) > (size_t)max_lds && b->wpw < 4) b->wpw *= 2;
-    if (batch_lds(b, b->wpw) > (size_t)max_lds) {
+    while (plan_lds(plan_of(b, b->wpw)) > (size_t)max_lds && b->wpw < 4) b->wpw *= 2;
+    if (plan_lds(plan_of(b, b->wpw)) > (size_t)max_lds) {
         delete b;
         return MUCA_E_SIZE;
     }
@@ -1024,7 +1163,7 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
         delete b;
         return rc;
     }
-    b->tab_bytes = choose_tab_bytes(b, b->wpw);
+    b->tab_bytes = plan_tab_bytes(plan_of(b, b->wpw));
     if (int rc = upload_batch(b)) {
         delete b;
         return rc;
@@ -1036,14 +1175,15 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
 int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t blocks)
 {
     if (!b || !(wpw == 0 || wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2)) return MUCA_E_INVAL;
-    if (batch_lds(b, wpw) > (size_t)b->jobs[0]->max_lds) return MUCA_E_SIZE;
+    if (plan_lds(plan_of(b, wpw)) > (size_t)b->jobs[0]->max_lds) return MUCA_E_SIZE;
     if (int rc = use_device(b->jobs[0])) return rc;
     const int old = b->wpw;
     b->wpw = wpw;
     b->bpl = bpl;
     b->blocks = blocks > 0 ? blocks : 0;
     if (old != wpw) {
-        b->tab_bytes = choose_tab_bytes(b, wpw);
+        b->tab_bytes = 0;
+        b->tab_bytes = plan_tab_bytes(plan_of(b, wpw));
         return upload_batch(b);
     }
     return MUCA_OK;
@@ -1053,10 +1193,11 @@ int muca_batch_get_launch(const muca_batch *b, int32_t *waves_per_walker, int32_
                           int32_t *lds_bytes)
 {
     if (!b) return MUCA_E_INVAL;
+    const BatchPlan p = plan_of(b, b->wpw);
     if (waves_per_walker)
-        for (size_t k = 0; k < b->jobs.size(); ++k) waves_per_walker[k] = tile_wpw(b, b->wpw, k);
+        for (int k = 0; k < p.n; ++k) waves_per_walker[k] = p.wpw_of(k);
     if (blocks_per_lane) *blocks_per_lane = b->bpl;
-    if (lds_bytes) *lds_bytes = (int32_t)(batch_lds(b, b->wpw) + b->tab_bytes);
+    if (lds_bytes) *lds_bytes = (int32_t)(plan_lds(p) + p.tab_bytes);
     return MUCA_OK;
 }
 
@@ -1068,25 +1209,10 @@ int muca_batch_sweep(muca_batch *b, int64_t n_sweeps, uint32_t flags)
     if (int rc = use_device(b->jobs[0])) return rc;
     const size_t off_tiles = align_up(b->jobs.size() * sizeof(BatchJob), 256);
     const size_t off_counter = off_tiles + align_up(b->total_walkers * sizeof(int2), 256);
-    BatchArgs a;
-    a.jobs = reinterpret_cast<const BatchJob *>(b->dev);
-    a.tiles = reinterpret_cast<const int2 *>(b->dev + off_tiles);
-    a.n_tiles = b->n_tiles;
-    a.counter = reinterpret_cast<unsigned *>(b->dev + off_counter);
-    a.lds_off_lat = kLdsFixed;
-    a.lds_off_tab = (int)batch_lds(b, b->wpw);
-    const bool record = (flags & MUCA_RECORD) != 0;
-    int64_t left = n_sweeps;
-    while (left > 0) {
-        const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
-        a.n_sweeps = chunk;
-        HIP_TRY(launch_zero(b->dev + off_counter, 16, b->stream));
-        HIP_TRY(launch_batch(a, b->wpw, b->bpl, record, batch_lds(b, b->wpw) + b->tab_bytes, b->blocks, b->stream));
-        left -= chunk;
-    }
-    if (record)
-        for (muca_job *j : b->jobs) j->recorded += n_sweeps;
-    return MUCA_OK;
+    return enqueue_batch(plan_of(b, b->wpw), b->bpl, b->blocks, reinterpret_cast<const BatchJob *>(b->dev),
+                         reinterpret_cast<const int2 *>(b->dev + off_tiles), b->n_tiles,
+                         reinterpret_cast<unsigned *>(b->dev + off_counter), n_sweeps, (flags & MUCA_RECORD) != 0,
+                         b->stream);
 }
 
 void muca_batch_free(muca_batch *b)
@@ -1095,6 +1221,53 @@ void muca_batch_free(muca_batch *b)
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
     delete b;
+}
+
+int muca_batch_sweep_static(muca_job *const *jobs, int32_t n_jobs, int64_t n_sweeps, uint32_t flags)
+{
+    if (int rc = check_job_list(jobs, n_jobs)) return rc;
+    if (n_sweeps < 0 || (flags & ~MUCA_RECORD)) return MUCA_E_INVAL;
+    if (n_jobs > kStaticMaxJobs) return MUCA_E_SIZE;
+    if (n_sweeps > MUCA_MAX_SWEEPS_PER_CALL) return MUCA_E_OVERFLOW;
+    // the launch shape muca_batch_create picks by default: one wave per
+    // walker, more only when the lattice slots do not fit in LDS
+    BatchPlan p;
+    p.jobs = jobs;
+    p.n = n_jobs;
+    p.wpw = 1;
+    p.job_wpw = nullptr;
+    p.tab_bytes = 0;
+    const int max_lds = jobs[0]->max_lds;
+    while (plan_lds(p) > (size_t)max_lds && p.wpw < 4) p.wpw *= 2;
+    if (plan_lds(p) > (size_t)max_lds) return MUCA_E_SIZE;
+    if (count_tiles(p) > kStaticMaxTiles) return MUCA_E_SIZE;
+    p.tab_bytes = plan_tab_bytes(p);
+    if (n_sweeps == 0) return MUCA_OK;
+    const int device = jobs[0]->device;
+    if (int rc = use_device(jobs[0])) return rc;
+    StaticScratch *st = nullptr;
+    {
+        std::lock_guard<std::mutex> guard(g_static_lock);
+        if (device >= 0 && device < kMaxDevices) {
+            st = g_static[device];
+            if (!st && g_static_error[device] != hipSuccess)
+                return fail_device(g_static_error[device], "hipGetSymbolAddress(scratch)");
+        }
+    }
+    if (!st) return MUCA_E_STATE;
+    std::lock_guard<std::mutex> guard(st->lock);
+    HIP_TRY(hipEventSynchronize(st->staged));  // the previous upload has read the host images
+    heaviest_first(jobs, n_jobs, st->order);
+    const int n_tiles = fill_batch(p, st->order, st->host_jobs, st->host_tiles);
+    hipStream_t stream = jobs[0]->stream;
+    HIP_TRY(hipMemcpyAsync(st->dev, st->host_jobs, sizeof(BatchJob) * (size_t)n_jobs, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(st->dev + kStaticOffTiles, st->host_tiles, sizeof(int2) * (size_t)n_tiles,
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(st->staged, stream));
+    return enqueue_batch(p, 1, 0, reinterpret_cast<const BatchJob *>(st->dev),
+                         reinterpret_cast<const int2 *>(st->dev + kStaticOffTiles), n_tiles,
+                         reinterpret_cast<unsigned *>(st->dev + kStaticOffCounter), n_sweeps,
+                         (flags & MUCA_RECORD) != 0, stream);
 }
 
 const char *muca_strerror(int code)

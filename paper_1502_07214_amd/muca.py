@@ -30,7 +30,7 @@ EXPORTS = (
     "muca_read_accum", "muca_reset_accum", "muca_set_stats", "muca_read_stats", "muca_set_launch", "muca_get_launch", "muca_host_tables",
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
     "muca_batch_set_launch", "muca_batch_get_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
-    "muca_reweight_hist", "muca_reweight_hist_sums", "muca_set_recursion",
+    "muca_reweight_hist", "muca_reweight_hist_sums", "muca_set_recursion", "muca_batch_sweep_static",
 )
 
 # weight recursion flags (muca_set_recursion)
@@ -96,6 +96,7 @@ def lib():
     L.muca_batch_set_launch.argtypes = [vp, i32, i32, i32]
     L.muca_batch_get_launch.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.muca_batch_sweep.argtypes = [vp, i64, u32]
+    L.muca_batch_sweep_static.argtypes = [P(vp), i32, i64, u32]
     L.muca_batch_free.argtypes = [vp]
     L.muca_batch_free.restype = None
     L.muca_flatness.argtypes = [P(i64), i32, i32, P(dbl)]
@@ -361,3 +362,12 @@ class MucaBatch:
             self.free()
         except Exception:
             pass
+
+
+def batch_sweep_static(jobs: Sequence[MucaJob], n_sweeps: int, record: bool = False):
+    """muca_batch_sweep_static: one batched sweep of the jobs (same device and
+    stream) whose job table and work list sit in the library's static device
+    array, for callers that cannot allocate."""
+    arr = (ctypes.c_void_p * len(jobs))(*[j._h.value for j in jobs])
+    _check(lib().muca_batch_sweep_static(arr, len(jobs), int(n_sweeps), MUCA_RECORD if record else 0),
+           "muca_batch_sweep_static")
