@@ -170,6 +170,27 @@ int muca_set_weights(muca_job *job, const double *lnW);
 /* Copy the job's current weights (V+1 doubles) to lnW_out. */
 int muca_get_weights(const muca_job *job, double *lnW_out);
 
+/* Confine the job's walkers to the E_Delta window [lo, hi] (0 <= lo < hi <=
+ * V).  The paper iterates the weights over all of [0, V] (Sec. II); a job
+ * that only needs Delta in some range (its canonical E_Delta distributions
+ * lie inside the window) converges over the window alone:
+ *   - moves that would leave the window are rejected (R_+[hi] = R_-[lo] = 0),
+ *     so inside it the chain is the Metropolis chain of exp(-beta E_J) W(E_Delta)
+ *     restricted to the window;
+ *   - the weights outside become walls falling by kappa = 12 beta + ln(2V) + 1
+ *     per bin away from the window: a walker outside accepts every move towards
+ *     it and enters in a few sweeps, then stays;
+ *   - muca_update_weights updates, extrapolates and measures flatness over the
+ *     window only (entries outside it are not used) and rebuilds the walls;
+ *     muca_set_weights keeps the window and rebuilds the walls;
+ *   - MUCA_RECORD adds to the production sums only measurements inside it.
+ * The window [0, V] (the default) changes nothing.  Clears the recursion
+ * statistics and the production sums.  MUCA_E_INVAL on a bad range. */
+int muca_set_window(muca_job *job, int32_t lo, int32_t hi);
+
+/* The job's window (lo, hi); either pointer may be NULL. */
+int muca_get_window(const muca_job *job, int32_t *lo, int32_t *hi);
+
 /* Step "reweight" (Sec. II time-series reweighting; Eqs. (FieldDerivative),
  * (sph)): canonical expectation values at (beta, delta[k]) for k < n_delta from
  * the production sums and the weights they were recorded under.  Runs one
@@ -315,10 +336,16 @@ int muca_batch_sweep_static(muca_job *const *jobs, int32_t n_jobs, int64_t n_swe
  * E_Delta; 0 when the window holds no entries. */
 int muca_flatness(const int64_t *hist, int32_t lo, int32_t hi, double *flatness_out);
 
-/* Host-only: the threshold tables of the acceptance rule for (L, T, lnW):
- * Bp (25), Rp (V+1) and Rm (V+1) doubles.  Used to check that the tables are
- * bitwise identical to an independent implementation on the same host. */
-int muca_host_tables(int32_t L, double T, const double *lnW, double *Bp, double *Rp, double *Rm);
+/* Host-only: the threshold tables of the acceptance rule for (L, T, lnW) and
+ * the window [lo, hi] (0, V: none): Bp (25), Rp (V+1) and Rm (V+1) doubles.
+ * Used to check that the tables are bitwise identical to an independent
+ * implementation on the same host. */
+int muca_host_tables(int32_t L, double T, const double *lnW, int32_t lo, int32_t hi, double *Bp, double *Rp,
+                     double *Rm);
+
+/* Host-only: replace lnW (V+1 doubles) outside the window [lo, hi] by the walls
+ * muca_set_window uses. */
+int muca_host_walls(int32_t L, double T, int32_t lo, int32_t hi, double *lnW);
 
 /* Host-only: the colour-major visiting order, order[p] = site index (V int32). */
 int muca_host_order(int32_t L, int32_t *order);

@@ -76,12 +76,20 @@ def lib():
         L.orc_accept.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_accept.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, i8p, i64p,
-                              dp, ctypes.c_int64, ctypes.c_int, i64p, i64p, u64p, u64p, ctypes.c_int]
+                              dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p, i64p, u64p, u64p,
+                              ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
         L.orc_update_weights.argtypes = [ctypes.c_int, i64p, dp]
         L.orc_update_weights.restype = ctypes.c_double
         L.orc_update_weights_ex.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_uint, dp, ctypes.POINTER(ctypes.c_uint8)]
         L.orc_update_weights_ex.restype = ctypes.c_double
+        L.orc_update_weights_window.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, i64p, dp,
+                                                ctypes.c_uint, dp, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_update_weights_window.restype = ctypes.c_double
+        L.orc_tables_window.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_tables_window.restype = None
+        L.orc_window_walls.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_window_walls.restype = None
         _lib = L
     return _lib
 
@@ -133,6 +141,17 @@ def tables(V: int, beta: float, lnW: np.ndarray):
     return Bp, Rp, Rm
 
 
+def tables_window(V: int, beta: float, lnW: np.ndarray, lo: int, hi: int):
+    """Threshold tables with the moves out of the window [lo, hi] rejected."""
+    lw = np.ascontiguousarray(lnW, dtype=np.float64)
+    Bp = np.zeros(25, dtype=np.float64)
+    Rp = np.zeros(V + 1, dtype=np.float64)
+    Rm = np.zeros(V + 1, dtype=np.float64)
+    lib().orc_tables_window(V, float(beta), _ptr(lw, ctypes.c_double), int(lo), int(hi), _ptr(Bp, ctypes.c_double),
+                            _ptr(Rp, ctypes.c_double), _ptr(Rm, ctypes.c_double))
+    return Bp, Rp, Rm
+
+
 def accept(u31: int, dEJ: int, d: int, E: int, Bp, Rp, Rm) -> bool:
     return bool(lib().orc_accept(u31, dEJ, d, E, _ptr(Bp, ctypes.c_double), _ptr(Rp, ctypes.c_double),
                                  _ptr(Rm, ctypes.c_double)))
@@ -161,6 +180,7 @@ class OracleJob:
         self.state = np.zeros((n_walkers, 4), dtype=np.int64)
         lib().orc_init(L, seed, first_walker, n_walkers, _ptr(self.spins, ctypes.c_int8), _ptr(self.state, ctypes.c_int64))
         self.lnW = np.zeros(self.V + 1) if lnW is None else np.array(lnW, dtype=np.float64)
+        self.lo, self.hi = 0, self.V
         self.hist = np.zeros(self.V + 1, dtype=np.int64)
         self.reset_accum()
         self.threads_used = 0
@@ -174,6 +194,19 @@ class OracleJob:
         self.kacc = np.zeros(max(self.V, 1), dtype=np.float64)
         self.seen = np.zeros(self.V + 1, dtype=np.uint8)
 
+    def set_window(self, lo: int, hi: int):
+        """Confine the walkers to E_Delta in [lo, hi] (0 <= lo < hi <= V): moves
+        out of the window are rejected, the weights outside it become walls
+        towards it (orc_window_walls), the recursion and its flatness act on
+        the window only, and only measurements inside it are recorded.
+        Clears the recursion statistics and the production sums."""
+        if not (0 <= lo < hi <= self.V):
+            raise ValueError("window must satisfy 0 <= lo < hi <= V")
+        self.lo, self.hi = int(lo), int(hi)
+        lib().orc_window_walls(self.V, self.beta, self.lo, self.hi, _ptr(self.lnW, ctypes.c_double))
+        self.set_recursion(self.recursion)
+        self.reset_accum()
+
     def reset_accum(self):
         self.acc = np.zeros((5, self.V + 1), dtype=np.int64)
         self.sm4_lo = np.zeros(self.V + 1, dtype=np.uint64)
@@ -183,7 +216,7 @@ class OracleJob:
         """n_sweeps sweeps of every walker; histogram entries are added to self.hist."""
         self.threads_used = lib().orc_run(
             self.L, self.beta, self.seed, self.first_walker, self.n_walkers, _ptr(self.spins, ctypes.c_int8),
-            _ptr(self.state, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double), int(n_sweeps),
+            _ptr(self.state, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double), self.lo, self.hi, int(n_sweeps),
             1 if record else 0, _ptr(self.hist, ctypes.c_int64), _ptr(self.acc, ctypes.c_int64),
             _ptr(self.sm4_lo, ctypes.c_uint64), _ptr(self.sm4_hi, ctypes.c_uint64), self.n_threads)
 
@@ -196,12 +229,12 @@ class OracleJob:
         """MUCA recursion on self.lnW (plain unless set_recursion chose a
         variant); returns the flatness of hist."""
         h = np.ascontiguousarray(hist, dtype=np.int64)
-        if self.recursion == 0:
+        if self.recursion == 0 and (self.lo, self.hi) == (0, self.V):
             self.seen |= (h > 0).astype(np.uint8)
             return float(lib().orc_update_weights(self.V, _ptr(h, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double)))
-        return float(lib().orc_update_weights_ex(self.V, _ptr(h, ctypes.c_int64), _ptr(self.lnW, ctypes.c_double),
-                                                 self.recursion, _ptr(self.kacc, ctypes.c_double),
-                                                 _ptr(self.seen, ctypes.c_uint8)))
+        return float(lib().orc_update_weights_window(self.V, self.beta, self.lo, self.hi, _ptr(h, ctypes.c_int64),
+                                                     _ptr(self.lnW, ctypes.c_double), self.recursion,
+                                                     _ptr(self.kacc, ctypes.c_double), _ptr(self.seen, ctypes.c_uint8)))
 
     def bin_sums(self) -> Dict[str, list]:
         """Per-bin sums of the recorded measurements as exact Python integers."""

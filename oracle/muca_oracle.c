@@ -167,6 +167,36 @@ void orc_tables(int V, double beta, const double *lnW, double *Bp, double *Rp, d
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Window (a job's Delta range confines its walkers to E_Delta in [lo, hi];  */
+/* the paper runs MUCA over all of [0, V], so this is an added reading).     */
+/* Inside the window the chain is the same Metropolis chain with the moves   */
+/* that would leave the window rejected: R_+[hi] = 0, R_-[lo] = 0.  Outside   */
+/* it the weights are walls falling by kappa = 12 beta + ln(2V) + 1 per bin */
+/* away from the window.  A walker outside then accepts every proposal that  */
+/* moves it towards the window (|dE_J| <= 12 and the wall factor e^kappa     */
+/* beats exp(-12 beta)), and accepts one away from it with probability at   */
+/* most 1/(2eV), which outweighs the at most V proposals per sweep that the  */
+/* entropy of E_Delta offers in that direction: it enters in a few sweeps,  */
+/* and once inside it never leaves.  With [lo, hi] = [0, V] nothing changes. */
+/* ------------------------------------------------------------------------ */
+void orc_tables_window(int V, double beta, const double *lnW, int lo, int hi, double *Bp, double *Rp,
+                       double *Rm)
+{
+    orc_tables(V, beta, lnW, Bp, Rp, Rm);
+    Rp[hi] = 0.0;
+    Rm[lo] = 0.0;
+}
+
+void orc_window_walls(int V, double beta, int lo, int hi, double *lnW)
+{
+    double kappa = 12.0 * beta + log(2.0 * (double)V) + 1.0;
+    for (int E = hi + 1; E <= V; E++)
+        lnW[E] = lnW[hi] - kappa * (double)(E - hi);
+    for (int E = lo - 1; E >= 0; E--)
+        lnW[E] = lnW[lo] - kappa * (double)(lo - E);
+}
+
 /* Decision for one proposal: one double product, one compare. */
 int orc_accept(uint32_t u31, int dEJ, int d, int E, const double *Bp, const double *Rp,
                const double *Rm)
@@ -204,6 +234,7 @@ typedef struct {
     int64_t *state;         /* n_walkers x 4: E_J, E_Delta, M, sweeps done */
     int w_begin, w_end;     /* local walker indices [w_begin, w_end) */
     int w_first;            /* global index of local walker 0 */
+    int lo, hi;             /* window: production sums record only E_Delta in [lo, hi] */
     int64_t *hist;          /* V+1, private to the thread */
     int64_t *acc;           /* 5 x (V+1): H, SJ, SJJ, SA, SM2, private */
     unsigned __int128 *sm4; /* V+1, private */
@@ -250,7 +281,7 @@ static void *orc_worker(void *arg)
             orc_sweep(t, t->w_first + w, s, st);
             int64_t ej = st[0], ed = st[1], m = st[2];
             t->hist[ed] += 1;
-            if (t->record) {
+            if (t->record && ed >= t->lo && ed <= t->hi) {
                 int64_t am = m < 0 ? -m : m;
                 t->acc[0 * (t->V + 1) + ed] += 1;
                 t->acc[1 * (t->V + 1) + ed] += ej;
@@ -266,14 +297,17 @@ static void *orc_worker(void *arg)
 
 /* Run n_sweeps sweeps of walkers [w_first, w_first + n_walkers) (global
  * walker indices; spins and state hold these walkers in order) under the weights lnW at
- * inverse temperature beta.  hist (V+1) and, when record != 0, acc
+ * inverse temperature beta, confined to the window [lo, hi] of E_Delta
+ * (0, V: no window).  hist (V+1) and, when record != 0, acc
  * (5 x (V+1): H, SJ, SJJ, SA, SM2) and sm4_lo/sm4_hi (V+1 each, the low and
- * high 64 bits of the 128-bit sums of M^4) are added to, not cleared.
+ * high 64 bits of the 128-bit sums of M^4) are added to, not cleared; the
+ * production sums take only measurements inside the window (a walker still
+ * on its way in is not in equilibrium under the walls).
  * Walkers are independent between weight updates, so they are split over
  * n_threads threads (0: one per online core); integer sums do not depend on
  * the split.  Returns the number of threads used. */
 int orc_run(int L, double beta, uint64_t seed, int w_first, int n_walkers, int8_t *spins, int64_t *state,
-            const double *lnW, int64_t n_sweeps, int record, int64_t *hist, int64_t *acc,
+            const double *lnW, int lo, int hi, int64_t n_sweeps, int record, int64_t *hist, int64_t *acc,
             uint64_t *sm4_lo, uint64_t *sm4_hi, int n_threads)
 {
     int V = L * L * L;
@@ -282,7 +316,7 @@ int orc_run(int L, double beta, uint64_t seed, int w_first, int n_walkers, int8_
     double *Rp = (double *)malloc(sizeof(double) * (V + 1));
     double *Rm = (double *)malloc(sizeof(double) * (V + 1));
     orc_order(L, order);
-    orc_tables(V, beta, lnW, Bp, Rp, Rm);
+    orc_tables_window(V, beta, lnW, lo, hi, Bp, Rp, Rm);
 
     if (n_threads <= 0)
         n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
@@ -298,6 +332,7 @@ int orc_run(int L, double beta, uint64_t seed, int w_first, int n_walkers, int8_
         t->L = L; t->V = V; t->seed = seed; t->order = order;
         t->Bp = Bp; t->Rp = Rp; t->Rm = Rm;
         t->n_sweeps = n_sweeps; t->record = record; t->w_first = w_first;
+        t->lo = lo; t->hi = hi;
         t->spins = spins; t->state = state;
         t->w_begin = (int)((int64_t)n_walkers * k / n_threads);
         t->w_end = (int)((int64_t)n_walkers * (k + 1) / n_threads);
@@ -392,17 +427,22 @@ double orc_update_weights(int V, const int64_t *hist, double *lnW)
 /*   in any iteration so far continue the slope of lnW over the last         */
 /*   k = min(8, hi - lo) bins inside the range, at each end.                  */
 /* kacc (V doubles) and seen (V+1 bytes) carry the state between iterations. */
-/* Returns the flatness of hist as orc_update_weights does.                   */
+/* With a window [lo, hi] (see orc_tables_window) all of this acts on the    */
+/* bins of the window only, as if it were the whole range: the flatness is   */
+/* min / mean over [lo, hi], the pairs are those inside it, the visited range */
+/* and its extrapolation stay inside it, and the walls outside are rebuilt  */
+/* from the new edge values.                                                */
+/* Returns the flatness of hist over [lo, hi].                               */
 /* ------------------------------------------------------------------------ */
-double orc_update_weights_ex(int V, const int64_t *hist, double *lnW, unsigned flags, double *kacc,
-                             uint8_t *seen)
+double orc_update_weights_window(int V, double beta, int lo, int hi, const int64_t *hist, double *lnW,
+                                 unsigned flags, double *kacc, uint8_t *seen)
 {
-    int64_t total = 0, least = hist[0];
+    int64_t total = 0, least = hist[lo];
     int any_seen = 0, reached_new = 0;
-    for (int E = 0; E <= V; E++)
+    for (int E = lo; E <= hi; E++)
         if (seen[E])
             any_seen = 1;
-    for (int E = 0; E <= V; E++) {
+    for (int E = lo; E <= hi; E++) {
         total += hist[E];
         if (hist[E] < least)
             least = hist[E];
@@ -413,13 +453,13 @@ double orc_update_weights_ex(int V, const int64_t *hist, double *lnW, unsigned f
         }
     }
     if ((flags & 1u) && any_seen && reached_new)
-        for (int E = 0; E < V; E++)
+        for (int E = lo; E < hi; E++)
             kacc[E] = 0.0;
     if (flags & 1u) {
         double *d = (double *)malloc(sizeof(double) * (size_t)(V > 0 ? V : 1));
-        for (int E = 0; E < V; E++)
+        for (int E = lo; E < hi; E++)
             d[E] = lnW[E + 1] - lnW[E];
-        for (int E = 0; E < V; E++) {
+        for (int E = lo; E < hi; E++) {
             int64_t a = hist[E], b = hist[E + 1];
             if (a > 0 && b > 0) {
                 double ha = (double)a, hb = (double)b;
@@ -432,33 +472,41 @@ double orc_update_weights_ex(int V, const int64_t *hist, double *lnW, unsigned f
                 d[E] = d[E] - log((double)b);
             }
         }
-        for (int E = 0; E < V; E++)
+        for (int E = lo; E < hi; E++)
             lnW[E + 1] = lnW[E] + d[E];
         free(d);
     } else {
-        for (int E = 0; E <= V; E++)
+        for (int E = lo; E <= hi; E++)
             if (hist[E] > 0)
                 lnW[E] = lnW[E] - log((double)hist[E]);
     }
     if (flags & 2u) {
-        int lo = -1, hi = -1;
-        for (int E = 0; E <= V; E++)
+        int slo = -1, shi = -1;
+        for (int E = lo; E <= hi; E++)
             if (seen[E]) {
-                if (lo < 0)
-                    lo = E;
-                hi = E;
+                if (slo < 0)
+                    slo = E;
+                shi = E;
             }
-        if (lo >= 0 && hi > lo) {
-            int k = hi - lo < 8 ? hi - lo : 8;
-            double s_hi = (lnW[hi] - lnW[hi - k]) / (double)k;
-            double s_lo = (lnW[lo + k] - lnW[lo]) / (double)k;
-            for (int E = hi + 1; E <= V; E++)
-                lnW[E] = lnW[hi] + (double)(E - hi) * s_hi;
-            for (int E = lo - 1; E >= 0; E--)
-                lnW[E] = lnW[lo] - (double)(lo - E) * s_lo;
+        if (slo >= 0 && shi > slo) {
+            int k = shi - slo < 8 ? shi - slo : 8;
+            double s_hi = (lnW[shi] - lnW[shi - k]) / (double)k;
+            double s_lo = (lnW[slo + k] - lnW[slo]) / (double)k;
+            for (int E = shi + 1; E <= hi; E++)
+                lnW[E] = lnW[shi] + (double)(E - shi) * s_hi;
+            for (int E = slo - 1; E >= lo; E--)
+                lnW[E] = lnW[slo] - (double)(slo - E) * s_lo;
         }
     }
+    orc_window_walls(V, beta, lo, hi, lnW);
     if (total == 0)
         return 0.0;
-    return (double)least / ((double)total / (double)(V + 1));
+    return (double)least / ((double)total / (double)(hi - lo + 1));
+}
+
+/* The recursion over the whole range [0, V] (no window, no walls). */
+double orc_update_weights_ex(int V, const int64_t *hist, double *lnW, unsigned flags, double *kacc,
+                             uint8_t *seen)
+{
+    return orc_update_weights_window(V, 0.0, 0, V, hist, lnW, flags, kacc, seen);
 }

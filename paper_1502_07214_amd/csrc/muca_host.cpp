@@ -108,8 +108,9 @@ Layout make_layout(const muca_params *p)
 
 // Acceptance thresholds (Sec. II): Bp[k+12] = 2^31 exp(-beta k), k = dE_J in
 // [-12, 12]; Rp[E] = exp(lnW[E+1] - lnW[E]) (0 at E = V); Rm[E] =
-// exp(lnW[E-1] - lnW[E]) (0 at E = 0).
-void compute_tables(int V, double beta, const double *lnW, double *Bp, double *Rp, double *Rm)
+// exp(lnW[E-1] - lnW[E]) (0 at E = 0).  A window [lo, hi] rejects the moves
+// that would leave it: Rp[hi] = Rm[lo] = 0 ([0, V]: no change).
+void compute_tables(int V, double beta, const double *lnW, int lo, int hi, double *Bp, double *Rp, double *Rm)
 {
     for (int k = 0; k < 25; ++k) {
         const double dE = (double)(k - 12);
@@ -119,6 +120,21 @@ void compute_tables(int V, double beta, const double *lnW, double *Bp, double *R
         Rp[E] = E < V ? std::exp(lnW[E + 1] - lnW[E]) : 0.0;
         Rm[E] = E > 0 ? std::exp(lnW[E - 1] - lnW[E]) : 0.0;
     }
+    Rp[hi] = 0.0;
+    Rm[lo] = 0.0;
+}
+
+// Weights outside a window [lo, hi]: walls that fall by kappa = 12 beta +
+// ln(2V) + 1 per bin away from it.  A walker outside accepts every proposal
+// towards the window (the wall factor beats exp(-beta dE_J) for |dE_J| <= 12)
+// and one away from it with probability at most 1/(2eV), which outweighs the
+// at most V such proposals per sweep that the entropy of E_Delta offers: it
+// enters in a few sweeps and, the tables confining it, never leaves.
+void window_walls(int V, double beta, int lo, int hi, double *lnW)
+{
+    const double kappa = 12.0 * beta + std::log(2.0 * (double)V) + 1.0;
+    for (int E = hi + 1; E <= V; ++E) lnW[E] = lnW[hi] - kappa * (double)(E - hi);
+    for (int E = lo - 1; E >= 0; --E) lnW[E] = lnW[lo] - kappa * (double)(lo - E);
 }
 
 int query_max_lds(int device)
@@ -148,6 +164,8 @@ struct muca_job {
     uint32_t rec_flags;
     std::vector<double> kacc;
     std::vector<uint8_t> seen;
+    // E_Delta window [win_lo, win_hi] the walkers are confined to ([0, V]: none)
+    int win_lo, win_hi;
     // launch shape
     int wpw, bpl, lds_tables_req;
     // pinned staging
@@ -262,7 +280,7 @@ int upload_tables(muca_job *j)
     double *lw = reinterpret_cast<double *>(j->pin_tables + g.off_lnw);
     std::vector<double> Rp(g.V + 1), Rm(g.V + 1);
     for (int k = 0; k < 32; ++k) Bp[k] = 0.0;
-    compute_tables(g.V, j->beta, j->lnW.data(), Bp, Rp.data(), Rm.data());
+    compute_tables(g.V, j->beta, j->lnW.data(), j->win_lo, j->win_hi, Bp, Rp.data(), Rm.data());
     for (int k = 0; k < 2 * (g.V + 1 + 2 * kRPad); ++k) R[k] = 0.0;
     for (int E = 0; E <= g.V; ++E) {
         R[2 * (E + kRPad)] = Rm[E];
@@ -338,6 +356,8 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
     j->rec_flags = 0u;
     j->kacc.assign(std::max(g.V, 1), 0.0);
     j->seen.assign(g.V + 1, 0);
+    j->win_lo = 0;
+    j->win_hi = g.V;
 
     auto bail = [&](int rc) {
         muca_free(j);
@@ -433,6 +453,8 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     for (int c = 0; c <= kMaxClasses; ++c) a.cls[c] = g.cls[c];
     a.k0 = j->k0;
     a.k1 = j->k1;
+    a.rec_lo = j->win_lo;
+    a.rec_hi = j->win_hi;
     a.lds_hist = pl.lds_hist ? 1 : 0;
     a.lds_off_hist = pl.off_hist;
     a.lds_off_lat = pl.off_lat;
@@ -484,11 +506,11 @@ namespace {
 // inverse Poisson variance k = H(E) H(E+1) / (H(E) + H(E+1)); a pair with one
 // visited bin takes the plain step; the weights are rebuilt upwards from bin 0.
 // The caller restarts the sums when an iteration reaches a new bin.
-void accumulated_step(int V, const int64_t *hist, double *lnW, double *kacc)
+void accumulated_step(int lo, int hi, const int64_t *hist, double *lnW, double *kacc)
 {
-    std::vector<double> d(std::max(V, 1));
-    for (int E = 0; E < V; ++E) d[E] = lnW[E + 1] - lnW[E];
-    for (int E = 0; E < V; ++E) {
+    std::vector<double> d(std::max(hi, 1));
+    for (int E = lo; E < hi; ++E) d[E] = lnW[E + 1] - lnW[E];
+    for (int E = lo; E < hi; ++E) {
         const int64_t a = hist[E], b = hist[E + 1];
         if (a > 0 && b > 0) {
             const double ha = (double)a, hb = (double)b;
@@ -501,15 +523,15 @@ void accumulated_step(int V, const int64_t *hist, double *lnW, double *kacc)
             d[E] = d[E] - std::log((double)b);
         }
     }
-    for (int E = 0; E < V; ++E) lnW[E + 1] = lnW[E] + d[E];
+    for (int E = lo; E < hi; ++E) lnW[E + 1] = lnW[E] + d[E];
 }
 
-// Bins outside the visited range [lo, hi] continue the mean slope of the last
-// min(8, hi - lo) differences inside it, at each end.
-void extrapolate_edges(int V, const uint8_t *seen, double *lnW)
+// Bins of the window [wlo, whi] outside the visited range [lo, hi] continue
+// the mean slope of the last min(8, hi - lo) differences inside it, at each end.
+void extrapolate_edges(int wlo, int whi, const uint8_t *seen, double *lnW)
 {
     int lo = -1, hi = -1;
-    for (int E = 0; E <= V; ++E)
+    for (int E = wlo; E <= whi; ++E)
         if (seen[E]) {
             if (lo < 0) lo = E;
             hi = E;
@@ -518,8 +540,8 @@ void extrapolate_edges(int V, const uint8_t *seen, double *lnW)
     const int k = std::min(hi - lo, 8);
     const double s_hi = (lnW[hi] - lnW[hi - k]) / (double)k;
     const double s_lo = (lnW[lo + k] - lnW[lo]) / (double)k;
-    for (int E = hi + 1; E <= V; ++E) lnW[E] = lnW[hi] + (double)(E - hi) * s_hi;
-    for (int E = lo - 1; E >= 0; --E) lnW[E] = lnW[lo] - (double)(lo - E) * s_lo;
+    for (int E = hi + 1; E <= whi; ++E) lnW[E] = lnW[hi] + (double)(E - hi) * s_hi;
+    for (int E = lo - 1; E >= wlo; --E) lnW[E] = lnW[lo] - (double)(lo - E) * s_lo;
 }
 
 }  // namespace
@@ -531,10 +553,13 @@ int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, doubl
     for (int E = 0; E <= V; ++E)
         if (hist[E] < 0) return MUCA_E_INVAL;
     if (int rc = use_device(j)) return rc;
-    int64_t sum = 0, least = hist[0];
+    // everything acts on the window: entries outside it (walkers on their
+    // way in) are not used
+    const int lo = j->win_lo, hi = j->win_hi;
+    int64_t sum = 0, least = hist[lo];
     bool any_seen = false, reached_new = false;
-    for (int E = 0; E <= V; ++E) any_seen = any_seen || j->seen[E];
-    for (int E = 0; E <= V; ++E) {
+    for (int E = lo; E <= hi; ++E) any_seen = any_seen || j->seen[E];
+    for (int E = lo; E <= hi; ++E) {
         sum += hist[E];
         least = std::min(least, hist[E]);
         if (hist[E] > 0) {
@@ -545,16 +570,17 @@ int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, doubl
     // estimates sampled before the range grew are biased by the part that was
     // out of reach: the accumulated statistics restart
     if ((j->rec_flags & MUCA_REC_ACCUMULATED) && any_seen && reached_new)
-        std::fill(j->kacc.begin(), j->kacc.end(), 0.0);
+        std::fill(j->kacc.begin() + lo, j->kacc.begin() + hi, 0.0);
     if (j->rec_flags & MUCA_REC_ACCUMULATED) {
-        accumulated_step(V, hist, j->lnW.data(), j->kacc.data());
+        accumulated_step(lo, hi, hist, j->lnW.data(), j->kacc.data());
     } else {
         // W <- W / H on the visited bins (plain multicanonical recursion)
-        for (int E = 0; E <= V; ++E)
+        for (int E = lo; E <= hi; ++E)
             if (hist[E] > 0) j->lnW[E] = j->lnW[E] - std::log((double)hist[E]);
     }
-    if (j->rec_flags & MUCA_REC_EXTRAPOLATE) extrapolate_edges(V, j->seen.data(), j->lnW.data());
-    if (flatness_out) *flatness_out = sum > 0 ? (double)least / ((double)sum / (double)(V + 1)) : 0.0;
+    if (j->rec_flags & MUCA_REC_EXTRAPOLATE) extrapolate_edges(lo, hi, j->seen.data(), j->lnW.data());
+    window_walls(V, j->beta, lo, hi, j->lnW.data());
+    if (flatness_out) *flatness_out = sum > 0 ? (double)least / ((double)sum / (double)(hi - lo + 1)) : 0.0;
     if (lnW_out) std::memcpy(lnW_out, j->lnW.data(), sizeof(double) * (V + 1));
     if (int rc = upload_tables(j)) return rc;
     return clear_accum(j);
@@ -567,8 +593,30 @@ int muca_set_weights(muca_job *j, const double *lnW)
         if (!std::isfinite(lnW[E])) return MUCA_E_INVAL;
     if (int rc = use_device(j)) return rc;
     j->lnW.assign(lnW, lnW + j->g.V + 1);
+    window_walls(j->g.V, j->beta, j->win_lo, j->win_hi, j->lnW.data());
     if (int rc = upload_tables(j)) return rc;
     return clear_accum(j);
+}
+
+int muca_set_window(muca_job *j, int32_t lo, int32_t hi)
+{
+    if (!j || lo < 0 || hi > j->g.V || lo >= hi) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    j->win_lo = lo;
+    j->win_hi = hi;
+    window_walls(j->g.V, j->beta, lo, hi, j->lnW.data());
+    j->kacc.assign(std::max(j->g.V, 1), 0.0);
+    j->seen.assign(j->g.V + 1, 0);
+    if (int rc = upload_tables(j)) return rc;
+    return clear_accum(j);
+}
+
+int muca_get_window(const muca_job *j, int32_t *lo, int32_t *hi)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (lo) *lo = j->win_lo;
+    if (hi) *hi = j->win_hi;
+    return MUCA_OK;
 }
 
 int muca_get_weights(const muca_job *j, double *lnW_out)
@@ -807,10 +855,20 @@ int muca_flatness(const int64_t *hist, int32_t lo, int32_t hi, double *flatness_
     return MUCA_OK;
 }
 
-int muca_host_tables(int32_t L, double T, const double *lnW, double *Bp, double *Rp, double *Rm)
+int muca_host_tables(int32_t L, double T, const double *lnW, int32_t lo, int32_t hi, double *Bp, double *Rp,
+                     double *Rm)
 {
     if (L < MUCA_L_MIN || L > MUCA_L_MAX || !(T > 0.0) || !lnW || !Bp || !Rp || !Rm) return MUCA_E_INVAL;
-    compute_tables(L * L * L, beta_of(T), lnW, Bp, Rp, Rm);
+    if (lo < 0 || hi > L * L * L || lo >= hi) return MUCA_E_INVAL;
+    compute_tables(L * L * L, beta_of(T), lnW, lo, hi, Bp, Rp, Rm);
+    return MUCA_OK;
+}
+
+int muca_host_walls(int32_t L, double T, int32_t lo, int32_t hi, double *lnW)
+{
+    if (L < MUCA_L_MIN || L > MUCA_L_MAX || !(T > 0.0) || !lnW) return MUCA_E_INVAL;
+    if (lo < 0 || hi > L * L * L || lo >= hi) return MUCA_E_INVAL;
+    window_walls(L * L * L, beta_of(T), lo, hi, lnW);
     return MUCA_OK;
 }
 
@@ -935,6 +993,8 @@ int fill_batch(const BatchPlan &p, const int *order, BatchJob *bj, int2 *tiles)
         for (int c = 0; c <= kMaxClasses; ++c) J.cls[c] = g.cls[c];
         J.k0 = j->k0;
         J.k1 = j->k1;
+        J.rec_lo = j->win_lo;
+        J.rec_hi = j->win_hi;
         J.lds_tables = p.tab_bytes > 0 && job_tab_bytes(j) <= p.tab_bytes ? 1 : 0;
         J.wpw = p.wpw_of(k);
     }

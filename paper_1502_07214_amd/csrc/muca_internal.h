@@ -45,6 +45,7 @@ struct SweepArgs {
     int pass_p0[kMaxCachedPasses], pass_p1[kMaxCachedPasses], pass_jbase[kMaxCachedPasses];
     unsigned pass_sync;            // bit k: synchronise after pass k (end of a colour class)
     uint32_t k0, k1;
+    int rec_lo, rec_hi;            // production sums record only E_Delta in [rec_lo, rec_hi]
     int n_sweeps;
     int lds_hist;                  // 1: histogram in LDS, flushed at the end
     int lds_off_hist, lds_off_lat, lds_off_r, lds_off_nb;
@@ -89,6 +90,7 @@ struct BatchJob {
     int V, Vp, n_walkers, n_classes;
     int cls[kMaxClasses + 1];
     uint32_t k0, k1;
+    int rec_lo, rec_hi;      // production sums record only E_Delta in [rec_lo, rec_hi]
     int lds_tables;          // 1: thresholds and neighbour table staged in LDS for this job's tiles
     int wpw;                 // waves per walker of this job's tiles (1 or 4) in a per-job launch
 };

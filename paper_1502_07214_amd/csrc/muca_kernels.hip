@@ -486,7 +486,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
                     m += sRed[2 * (slot * WPW + v) + 1];
                 }
             }
-            if (live && lg == 0) {
+            if (live && lg == 0 && wk.ED >= a.rec_lo && wk.ED <= a.rec_hi) {
                 const int ED = wk.ED;
                 const long long EJ = (long long)(int)((unsigned)EJ0 + ej);
                 const long long M = (long long)(int)((unsigned)M0 + m);
@@ -608,6 +608,8 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
         a.pass_sync = 0u;
         a.k0 = J.k0;
         a.k1 = J.k1;
+        a.rec_lo = J.rec_lo;
+        a.rec_hi = J.rec_hi;
         a.n_sweeps = b.n_sweeps;
         a.lds_hist = 0;
         a.lds_off_hist = kLdsFixed;

@@ -31,6 +31,7 @@ EXPORTS = (
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
     "muca_batch_set_launch", "muca_batch_get_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
     "muca_reweight_hist", "muca_reweight_hist_sums", "muca_set_recursion", "muca_batch_sweep_static",
+    "muca_set_window", "muca_get_window", "muca_host_walls",
 )
 
 # weight recursion flags (muca_set_recursion)
@@ -85,7 +86,10 @@ def lib():
     L.muca_read_stats.argtypes = [vp, P(i64), i32]
     L.muca_set_launch.argtypes = [vp, i32, i32, i32]
     L.muca_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
-    L.muca_host_tables.argtypes = [i32, dbl, P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.muca_host_tables.argtypes = [i32, dbl, P(dbl), i32, i32, P(dbl), P(dbl), P(dbl)]
+    L.muca_host_walls.argtypes = [i32, dbl, i32, i32, P(dbl)]
+    L.muca_set_window.argtypes = [vp, i32, i32]
+    L.muca_get_window.argtypes = [vp, P(i32), P(i32)]
     L.muca_host_order.argtypes = [i32, P(i32)]
     L.muca_strerror.argtypes = [ctypes.c_int]
     L.muca_strerror.restype = ctypes.c_char_p
@@ -131,13 +135,22 @@ def muca_query_sizes(L: int, T: float, n_walkers: int, seed: int = 0, max_delta:
     return dict(zip(("lattice", "walker_state", "hist", "tables", "accum", "obs"), [x.value for x in s]))
 
 
-def muca_host_tables(L: int, T: float, lnW: np.ndarray):
+def muca_host_tables(L: int, T: float, lnW: np.ndarray, window=None):
     V = L ** 3
+    lo, hi = (0, V) if window is None else window
     lw = np.ascontiguousarray(lnW, dtype=np.float64)
     Bp, Rp, Rm = np.zeros(25), np.zeros(V + 1), np.zeros(V + 1)
     D = ctypes.c_double
-    _check(lib().muca_host_tables(L, float(T), _p(lw, D), _p(Bp, D), _p(Rp, D), _p(Rm, D)), "muca_host_tables")
+    _check(lib().muca_host_tables(L, float(T), _p(lw, D), int(lo), int(hi), _p(Bp, D), _p(Rp, D), _p(Rm, D)),
+           "muca_host_tables")
     return Bp, Rp, Rm
+
+
+def muca_host_walls(L: int, T: float, lo: int, hi: int, lnW: np.ndarray) -> np.ndarray:
+    """lnW with the bins outside [lo, hi] replaced by the window's walls."""
+    lw = np.array(lnW, dtype=np.float64)
+    _check(lib().muca_host_walls(L, float(T), int(lo), int(hi), _p(lw, ctypes.c_double)), "muca_host_walls")
+    return lw
 
 
 def muca_flatness(hist: np.ndarray, lo: int, hi: int) -> float:
@@ -258,6 +271,16 @@ class MucaJob:
         REC_EXTRAPOLATE or 0 for the plain recursion); resets its statistics."""
         _check(lib().muca_set_recursion(self._h, int(flags)), "muca_set_recursion")
         self.recursion = int(flags)
+
+    def set_window(self, lo: int, hi: int):
+        """Confine the walkers to E_Delta in [lo, hi] (muca_set_window)."""
+        _check(lib().muca_set_window(self._h, int(lo), int(hi)), "muca_set_window")
+
+    @property
+    def window(self) -> tuple:
+        lo, hi = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().muca_get_window(self._h, ctypes.byref(lo), ctypes.byref(hi)), "muca_get_window")
+        return lo.value, hi.value
 
     def set_weights(self, lnW):
         w = np.ascontiguousarray(lnW, dtype=np.float64)

@@ -1,12 +1,16 @@
 """Serving loop: multicanonical jobs arriving over time, continuously batched.
 
-Requests arrive as a Poisson process.  Each is a MUCA job (L, T, walkers)
-whose weights start tilted towards the transition field Delta_mid(T), i.e.
-lnW(E) = -beta Delta_mid E, the canonical ensemble at Delta_mid (Sec. II: one
-multicanonical run per temperature is reweighted to nearby Delta).  A job
-iterates "S sweeps, merge histogram, update weights" until the merged
-histogram of an iteration is flat (min/mean > threshold over its E_Delta
-window) or it hits the iteration cap (then it is reported as censored).
+Requests arrive as a Poisson process.  Each is a MUCA job (L, T, walkers,
+Delta range) whose weights start tilted towards the transition field
+Delta_mid(T), i.e. lnW(E) = -beta Delta_mid E, the canonical ensemble at
+Delta_mid (Sec. II: one multicanonical run per temperature is reweighted to
+nearby Delta).  The Delta range fixes the job's E_Delta window (the bins the
+canonical distributions at the ends of the range populate, measured by two
+short canonical probes, see probe_windows); the walkers are confined to it.  A
+job iterates "S sweeps, merge histogram, update weights" until the merged
+histogram of an iteration is flat (min/mean > threshold over its window) or it
+hits the iteration cap or the run's wall budget (then it is reported as
+censored).
 
 Continuous batching: jobs are admitted from a FIFO queue while the resident
 walker count and device-memory footprint allow; every iteration of the loop is
@@ -56,21 +60,96 @@ class Request:
     n_walkers: int
     seed: int
     arrival: float  # seconds after the start of the run
+    delta_range: Optional[Tuple[float, float]] = None  # None: the whole E_Delta range [0, V]
 
 
 def poisson_requests(n: int, rate: float, seed: int = 0, L_range=(8, 24), T_range=(0.9, 2.0),
-                     walker_choices=(64, 128, 192, 256, 320, 384, 448, 512)) -> List[Request]:
+                     walker_choices=(64, 128, 192, 256, 320, 384, 448, 512),
+                     delta_halfwidth: Optional[float] = 0.1) -> List[Request]:
     """n requests with exponential inter-arrival gaps (mean 1/rate), L uniform
     in L_range (inclusive), T uniform in T_range, walkers uniform over
-    walker_choices; drawn from a seeded generator."""
+    walker_choices, drawn from a seeded generator; each asks for Delta in
+    Delta_mid(T) +- delta_halfwidth (None: the whole E_Delta range)."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n)
     arrivals = np.cumsum(gaps) - gaps[0]
     Ls = rng.integers(L_range[0], L_range[1] + 1, size=n)
     Ts = rng.uniform(T_range[0], T_range[1], size=n)
     Ws = rng.choice(np.asarray(walker_choices), size=n)
-    return [Request(i, int(Ls[i]), float(Ts[i]), int(Ws[i]), int(seed * 1_000_003 + i), float(arrivals[i]))
-            for i in range(n)]
+    out = []
+    for i in range(n):
+        dr = None
+        if delta_halfwidth is not None:
+            dm = delta_mid(float(Ts[i]))
+            dr = (dm - delta_halfwidth, dm + delta_halfwidth)
+        out.append(Request(i, int(Ls[i]), float(Ts[i]), int(Ws[i]), int(seed * 1_000_003 + i), float(arrivals[i]), dr))
+    return out
+
+
+@dataclass
+class ProbeConfig:
+    walkers: int = 32      # walkers per probe
+    relax: int = 100       # sweeps before measuring
+    measure: int = 100     # sweeps measured
+
+
+def _probe_margin(V: int) -> int:
+    return 2 + V // 100
+
+
+def probe_windows(requests: Sequence[Request], probe: ProbeConfig = ProbeConfig()) -> Dict[int, Tuple[int, int]]:
+    """E_Delta window of each request with a Delta range.
+
+    Reading (the paper iterates over all of [0, V]): the window is the range
+    of E_Delta that the canonical distributions at the two ends of the Delta
+    range populate.  Two canonical probes per job measure it (weights
+    lnW = -beta Delta_end E, probe.walkers walkers, probe.relax sweeps to
+    relax, then probe.measure sweeps whose E_Delta histogram is kept): at
+    Delta_lo from the fully ordered lattice (every spin +1) and at Delta_hi
+    from the empty one (every spin 0), so that each starts in the phase that
+    is stable at its end of the range (the low-Delta end favours occupied
+    sites, the high-Delta end vacancies).  The window runs from the lowest
+    E_Delta seen at Delta_hi to the highest seen at Delta_lo, widened by
+    2 + V/100 bins and clipped to [0, V].  The probes of all requests run in
+    one batched launch; their chains depend only on the request, so a job's
+    window is the same alone and in any mix."""
+    reqs = [r for r in requests if r.delta_range is not None]
+    if not reqs:
+        return {}
+    probes = []
+    for r in reqs:
+        V = r.L ** 3
+        beta = 1.0 / r.T
+        for end, (delta, fill) in enumerate(((min(r.delta_range), 1), (max(r.delta_range), 0))):
+            lnW = -(beta * delta) * np.arange(V + 1, dtype=np.float64)
+            job = MucaJob(r.L, r.T, probe.walkers, seed=(r.seed + ((end + 1) << 40)) & 0xFFFFFFFFFFFFFFFF,
+                          lnW=lnW, max_delta=1)
+            spins = np.full((probe.walkers, V), fill, dtype=np.int8)
+            state = np.tile(np.array([-3 * V * fill, V * fill, V * fill, 0], dtype=np.int64), (probe.walkers, 1))
+            job.write_state(spins, state)
+            probes.append(job)
+    batch = MucaBatch(probes) if len(probes) > 1 else None
+    for sweeps in (probe.relax, probe.measure):
+        if batch is not None:
+            batch.sweep(sweeps)
+        else:
+            probes[0].sweep(sweeps)
+        hists = [p.reduce_hist(reset=True) for p in probes]
+    if batch is not None:
+        batch.free()
+    out = {}
+    for k, r in enumerate(reqs):
+        V = r.L ** 3
+        lo_seen = np.flatnonzero(hists[2 * k + 1])
+        hi_seen = np.flatnonzero(hists[2 * k])
+        both = np.concatenate([lo_seen, hi_seen])
+        lo, hi = int(min(lo_seen.min(), both.min())), int(max(hi_seen.max(), both.max()))
+        m = _probe_margin(V)
+        lo, hi = max(0, lo - m), min(V, hi + m)
+        out[r.id] = (lo, hi)
+    for p in probes:
+        p.free()
+    return out
 
 
 @dataclass
@@ -82,6 +161,7 @@ class JobRecord:
     flatness: List[float] = field(default_factory=list)
     converged: bool = False
     attempts: int = 0
+    window: Tuple[int, int] = (0, 0)
 
     @property
     def latency(self) -> float:
@@ -93,23 +173,26 @@ class ServeConfig:
     sweeps: int = 500              # sweeps per iteration
     threshold: float = 0.5         # flatness min/mean that ends a job
     max_iterations: int = 2000     # iteration cap (job censored)
-    window: Tuple[float, float] = (0.0, 1.0)  # flatness window as fractions of V
     max_walkers: int = 32768       # resident walkers
     hbm_budget: int = 16 << 30     # resident device bytes
     shape: Optional[Tuple[int, int]] = None  # batched launch shape (None: library default)
     recursion: int = 0             # weight recursion flags (REC_ACCUMULATED | REC_EXTRAPOLATE; 0 plain)
+    probe: ProbeConfig = field(default_factory=ProbeConfig)  # Delta range -> E_Delta window
+    wall_budget: Optional[float] = None  # seconds; jobs unfinished by then are censored at it
 
 
 class _Live:
-    def __init__(self, rec: JobRecord, cfg: ServeConfig, now: float):
+    def __init__(self, rec: JobRecord, cfg: ServeConfig, now: float, window: Optional[Tuple[int, int]]):
         r = rec.req
         self.rec = rec
         self.job = MucaJob(r.L, r.T, r.n_walkers, seed=r.seed, lnW=tilted_weights(r.L, r.T), max_delta=1)
         if cfg.recursion:
             self.job.set_recursion(cfg.recursion)
         self.V = r.L ** 3
-        self.lo = int(round(cfg.window[0] * self.V))
-        self.hi = int(round(cfg.window[1] * self.V))
+        self.lo, self.hi = window if window is not None else (0, self.V)
+        if window is not None:
+            self.job.set_window(*window)
+        rec.window = (self.lo, self.hi)
         rec.admitted = now
 
     def step_done(self, cfg: ServeConfig, now: float) -> bool:
@@ -138,6 +221,18 @@ def _wait_until(t0: float, t: float):
         time.sleep(dt)
 
 
+def _censor_at_budget(records: Dict[int, JobRecord], arrived: Sequence[Request], budget: float):
+    """Jobs that arrived before the wall budget and have not finished are
+    censored at it: latency = budget - arrival, a lower bound."""
+    for r in arrived:
+        rec = records.get(r.id)
+        if rec is None:
+            rec = records[r.id] = JobRecord(r)
+        if math.isnan(rec.finished):
+            rec.finished = budget
+            rec.converged = False
+
+
 def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False, progress=None) -> dict:
     """Continuous batching over the request stream (real time).  progress, if
     given, is called with the finished job records as jobs finish."""
@@ -146,6 +241,7 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
     t0 = time.perf_counter()
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue: collections.deque = collections.deque()
+    arrived: List[Request] = []
     active: List[_Live] = []
     records: Dict[int, JobRecord] = {}
     kept = {}
@@ -157,24 +253,35 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
     attempts = 0
     while pending or queue or active:
         now = time.perf_counter() - t0
+        if cfg.wall_budget is not None and now >= cfg.wall_budget:
+            break
         while pending and pending[0].arrival <= now:
-            queue.append(pending.popleft())
-        changed = False
+            r = pending.popleft()
+            queue.append(r)
+            arrived.append(r)
+        admit = []
         while queue:
             r = queue[0]
             fb = footprint(r)
-            if active and (walkers + r.n_walkers > cfg.max_walkers or nbytes + fb > cfg.hbm_budget):
+            if (active or admit) and (walkers + r.n_walkers > cfg.max_walkers or nbytes + fb > cfg.hbm_budget):
                 break
             queue.popleft()
-            rec = JobRecord(r)
-            records[r.id] = rec
-            active.append(_Live(rec, cfg, time.perf_counter() - t0))
+            admit.append(r)
             walkers += r.n_walkers
             nbytes += fb
-            changed = True
+        if admit:
+            # the admitted jobs' windows: their probes in one batched launch
+            windows = probe_windows(admit, cfg.probe)
+            for r in admit:
+                rec = JobRecord(r)
+                records[r.id] = rec
+                active.append(_Live(rec, cfg, time.perf_counter() - t0, windows.get(r.id)))
+        changed = bool(admit)
         depth.append(len(queue))
         if not active:
-            _wait_until(t0, pending[0].arrival)
+            if pending:
+                _wait_until(t0, pending[0].arrival if cfg.wall_budget is None
+                            else min(pending[0].arrival, cfg.wall_budget))
             continue
         if len(active) == 1:
             # a lone job runs its own launch (its shape keeps neighbour
@@ -212,13 +319,22 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
             active = [a for a in active if a not in done]
     if batch is not None:
         batch.free()
+    if cfg.wall_budget is not None and (pending or queue or active):
+        _censor_at_budget(records, arrived, cfg.wall_budget)
+        for a in active:
+            if keep_jobs:
+                kept[a.rec.req.id] = a.job
+            else:
+                a.job.free()
     makespan = time.perf_counter() - t0
-    return _summary(records, makespan, attempts, launches, depth, kept)
+    out = _summary(records, makespan, attempts, launches, depth, kept)
+    out["not_arrived"] = len(pending)
+    return out
 
 
 def serve_plain(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False) -> dict:
     """Baseline: the same requests, one job at a time in arrival order, each
-    with its own plain launches."""
+    with its own probes and plain launches."""
     import torch
 
     t0 = time.perf_counter()
@@ -226,12 +342,22 @@ def serve_plain(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool =
     kept = {}
     attempts = 0
     launches = 0
-    for r in sorted(requests, key=lambda r: r.arrival):
+    order = sorted(requests, key=lambda r: r.arrival)
+    arrived: List[Request] = []
+    out_of_time = False
+    for r in order:
+        if cfg.wall_budget is not None and max(r.arrival, time.perf_counter() - t0) >= cfg.wall_budget:
+            out_of_time = True
+            break
         _wait_until(t0, r.arrival)
+        arrived.append(r)
         rec = JobRecord(r)
         records[r.id] = rec
-        live = _Live(rec, cfg, time.perf_counter() - t0)
+        live = _Live(rec, cfg, time.perf_counter() - t0, probe_windows([r], cfg.probe).get(r.id))
         while True:
+            if cfg.wall_budget is not None and time.perf_counter() - t0 >= cfg.wall_budget:
+                out_of_time = True
+                break
             live.job.sweep(cfg.sweeps)
             launches += 1
             attempts += r.n_walkers * live.V * cfg.sweeps
@@ -242,8 +368,17 @@ def serve_plain(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool =
             kept[r.id] = live.job
         else:
             live.job.free()
+        if out_of_time:
+            break
+    not_arrived = 0
+    if out_of_time:
+        late = [r for r in order if r.arrival < cfg.wall_budget]
+        _censor_at_budget(records, late, cfg.wall_budget)
+        not_arrived = len(order) - len(late)
     makespan = time.perf_counter() - t0
-    return _summary(records, makespan, attempts, launches, [0], kept)
+    out = _summary(records, makespan, attempts, launches, [0], kept)
+    out["not_arrived"] = not_arrived
+    return out
 
 
 def _summary(records, makespan, attempts, launches, depth, kept) -> dict:
@@ -255,6 +390,7 @@ def _summary(records, makespan, attempts, launches, depth, kept) -> dict:
         "censored": len(records) - len(conv),
         "makespan_s": makespan,
         "jobs_per_s": len(records) / makespan if makespan > 0 else 0.0,
+        "converged_per_s": len(conv) / makespan if makespan > 0 else 0.0,
         "attempts": attempts,
         "attempts_per_s": attempts / makespan if makespan > 0 else 0.0,
         "launches": launches,

@@ -110,12 +110,22 @@ def assert_obs_close(gpu, ref, beta, V, absm):
         assert np.all(np.abs(gpu[:, j] - ref[:, j]) <= 1e-12 * np.abs(ref[:, j]) + 1e-300), name
 
 
-def run_both(L, T, nw, seed, iterations, sweeps, production, deltas, launch=None, lnW=None, threads=0):
-    say(f"[parity] L={L} T={T} walkers={nw} seed={seed} it={iterations}x{sweeps} prod={production} launch={launch}")
+def run_both(L, T, nw, seed, iterations, sweeps, production, deltas, launch=None, lnW=None, threads=0, window=None,
+             recursion=0):
+    say(f"[parity] L={L} T={T} walkers={nw} seed={seed} it={iterations}x{sweeps} prod={production} launch={launch} "
+        f"window={window} recursion={recursion}")
     job = MucaJob(L, T, nw, seed=seed, lnW=lnW, max_delta=max(1, len(deltas)))
     if launch is not None:
         job.set_launch(*launch)
     o = oracle.OracleJob(L, T, nw, seed, lnW=lnW, n_threads=threads)
+    if recursion:
+        job.set_recursion(recursion)
+        o.set_recursion(recursion)
+    if window is not None:
+        job.set_window(*window)
+        o.set_window(*window)
+        assert job.window == tuple(window)
+        assert job.lnW.tobytes() == o.lnW.tobytes(), "walls differ"
     spins, state = job.read_state()
     assert np.array_equal(spins, o.spins), "initial lattices differ"
     assert np.array_equal(state, o.state), "initial energies differ"
@@ -404,3 +414,56 @@ def test_sum_of_m4_carries_past_64_bits(path):
     g = job.reweight([2.0, 3.0])
     assert np.all(np.abs(g[:, COL["mean_M4"]] - r[:, COL["mean_M4"]]) <= 1e-12 * np.abs(r[:, COL["mean_M4"]]))
     job.free()
+
+
+@pytest.mark.parametrize("recursion", [0, 3])
+def test_window_job_bit_exact(recursion):
+    """A job confined to an E_Delta window that holds its walkers' start (L=8,
+    T=1, start tilted to Delta* = 2.944, window [200, 420] of V = 512): every
+    histogram, weight array (walls included), lattice and production sum bit
+    for bit, for the plain and the accumulated + extrapolating recursion."""
+    L, T = 8, 1.0
+    lnW = -(2.944 / T) * np.arange(L ** 3 + 1)
+    run_both(L, T, 32, 17, 4, 200, 200, np.linspace(2.8, 3.1, 31), lnW=lnW, window=(200, 420),
+             recursion=recursion)
+
+
+@pytest.mark.parametrize("launch", [(1, 1, -1), (4, 1, 1), (2, 2, 0)])
+def test_window_entered_from_outside(launch):
+    """Random lattices sit near E_Delta = 2V/3 = 667, above the window [100, 400]
+    of L=10, T=2: the walls take the walkers in and the tables keep them there
+    (odd and even launch shapes); entries before they arrive fall outside the
+    window and are not used."""
+    run_both(10, 2.0, 12, 23, 3, 150, 100, np.linspace(2.3, 2.8, 11), window=(100, 400), launch=launch)
+
+
+def test_window_batched_equals_oracle():
+    """Windowed jobs in one batched launch: each equals its oracle replay."""
+    specs = [(8, 1.0, 16, 31, (150, 480)), (6, 2.0, 9, 32, (20, 120)), (12, 0.9, 8, 33, (400, 1700))]
+    jobs, ors = [], []
+    for L, T, n, seed, win in specs:
+        lnW = -(2.9 / T) * np.arange(L ** 3 + 1)
+        j = MucaJob(L, T, n, seed=seed, lnW=lnW, max_delta=1)
+        j.set_window(*win)
+        o = oracle.OracleJob(L, T, n, seed, lnW=lnW)
+        o.set_window(*win)
+        jobs.append(j)
+        ors.append(o)
+    say("[parity] windowed batch of 3 jobs")
+    batch = MucaBatch(jobs)
+    for it in range(3):
+        batch.sweep(60, record=(it == 2))
+        for j, o in zip(jobs, ors):
+            o.sweep(60, record=(it == 2))
+            hg, ho = j.reduce_hist(), o.take_hist()
+            assert np.array_equal(hg, ho)
+            if it < 2:
+                assert j.update_weights(hg) == o.update_weights(ho)
+                assert j.lnW.tobytes() == o.lnW.tobytes()
+    batch.free()
+    for j, o in zip(jobs, ors):
+        sg, so = j.read_accum(), o.bin_sums()
+        assert all(sg[k] == so[k] for k in ("H", "SJ", "SJJ", "SA", "SM2", "SM4"))
+        spins, state = j.read_state()
+        assert np.array_equal(spins, o.spins) and np.array_equal(state, o.state)
+        j.free()

@@ -1,6 +1,8 @@
 """Serving loop: a job served in a Poisson mix (continuous batching) gives the
 same iterations, flatness history, weights and final walker state as the same
 job served alone, bit for bit."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -17,8 +19,9 @@ def test_served_equals_alone():
     mix = serve(reqs, cfg, keep_jobs=True)
     assert mix["jobs"] == 6
     for r in reqs[:3]:
-        alone = serve_plain([Request(r.id, r.L, r.T, r.n_walkers, r.seed, 0.0)], cfg, keep_jobs=True)
+        alone = serve_plain([dataclasses.replace(r, arrival=0.0)], cfg, keep_jobs=True)
         a, b = mix["records"][r.id], alone["records"][r.id]
+        assert a.window == b.window
         assert a.iterations == b.iterations and a.flatness == b.flatness and a.converged == b.converged
         ja, jb = mix["jobs_kept"][r.id], alone["jobs_kept"][r.id]
         sa, sta = ja.read_state()
@@ -52,7 +55,7 @@ def test_lone_and_batched_launches_alternate():
     mix = serve(reqs, cfg, keep_jobs=True)
     assert mix["jobs"] == 3 and mix["censored"] == 3
     for r in reqs:
-        alone = serve_plain([Request(r.id, r.L, r.T, r.n_walkers, r.seed, 0.0)], cfg, keep_jobs=True)
+        alone = serve_plain([dataclasses.replace(r, arrival=0.0)], cfg, keep_jobs=True)
         a, b = mix["records"][r.id], alone["records"][r.id]
         assert a.iterations == b.iterations == 60 and a.flatness == b.flatness
         ja, jb = mix["jobs_kept"][r.id], alone["jobs_kept"][r.id]
@@ -63,3 +66,42 @@ def test_lone_and_batched_launches_alternate():
         jb.free()
     for j in mix["jobs_kept"].values():
         j.free()
+
+
+def test_large_windowed_jobs_served_equal_alone():
+    """Jobs at L = 16..20 with Delta ranges Delta_mid(T) +- 0.1 (windows from
+    the canonical probes), served in a mix of four, equal the same jobs served
+    alone: window, flatness history, weights and walkers bit for bit."""
+    reqs = [Request(0, 16, 0.95, 64, 101, 0.0, (2.85, 3.05)), Request(1, 20, 2.0, 64, 102, 0.0, (2.42, 2.62)),
+            Request(2, 18, 1.4182, 128, 103, 0.01, (2.7446, 2.9446)), Request(3, 6, 1.2, 64, 104, 0.02, (2.8, 3.0))]
+    cfg = ServeConfig(sweeps=40, threshold=0.5, max_iterations=6, max_walkers=1024)
+    print("[serve] windowed L=16..20 mix", flush=True)
+    mix = serve(reqs, cfg, keep_jobs=True)
+    assert mix["jobs"] == 4
+    for r in reqs[:3]:
+        a = mix["records"][r.id]
+        V = r.L ** 3
+        assert 0 <= a.window[0] < a.window[1] <= V and a.window != (0, V)
+        alone = serve_plain([dataclasses.replace(r, arrival=0.0)], cfg, keep_jobs=True)
+        b = alone["records"][r.id]
+        print(f"[serve] L={r.L} T={r.T} window {a.window} flatness {a.flatness[-1]:.3f}", flush=True)
+        assert a.window == b.window and a.iterations == b.iterations and a.flatness == b.flatness
+        ja, jb = mix["jobs_kept"][r.id], alone["jobs_kept"][r.id]
+        assert ja.window == jb.window == a.window
+        sa, sta = ja.read_state()
+        sb, stb = jb.read_state()
+        assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+        assert ja.lnW.tobytes() == jb.lnW.tobytes()
+        jb.free()
+    for j in mix["jobs_kept"].values():
+        j.free()
+
+
+def test_wall_budget_censors_unfinished_jobs():
+    reqs = poisson_requests(4, rate=100.0, seed=5, L_range=(12, 12), walker_choices=(64,))
+    cfg = ServeConfig(sweeps=200, threshold=0.99, max_iterations=10_000, wall_budget=1.5)
+    out = serve(reqs, cfg)
+    assert out["jobs"] == 4 and out["converged"] == 0 and out["censored"] == 4
+    assert all(abs(r.finished - 1.5) < 1e-9 for r in out["records"].values())
+    plain = serve_plain(reqs, cfg)
+    assert plain["censored"] == 4 and plain["jobs"] == 4

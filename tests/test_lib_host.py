@@ -40,6 +40,22 @@ def test_host_tables_bitwise_equal_oracle(L, T):
             assert x.tobytes() == y.tobytes()
 
 
+@pytest.mark.parametrize("L,T,lo,hi", [(2, 0.5, 2, 6), (4, 2.0, 10, 40), (12, 0.9, 300, 1500), (5, float("inf"), 0, 20),
+                                        (6, 1.4182, 100, 216)])
+def test_window_tables_and_walls_bitwise_equal_oracle(L, T, lo, hi):
+    """The window's thresholds and walls equal the oracle's bit for bit."""
+    V = L ** 3
+    lnW = np.cumsum(np.random.default_rng(L + lo).normal(0, 2.0, V + 1))
+    a = muca.muca_host_walls(L, T, lo, hi, lnW)
+    job = oracle.OracleJob(L, T, 1, 0, lnW=lnW)
+    job.set_window(lo, hi)
+    assert a.tobytes() == job.lnW.tobytes()
+    t = muca.muca_host_tables(L, T, a, window=(lo, hi))
+    u = oracle.tables_window(V, oracle.beta_of(T), a, lo, hi)
+    for x, y in zip(t, u):
+        assert x.tobytes() == y.tobytes()
+
+
 @pytest.mark.parametrize("L", range(2, 13))
 def test_host_order_equals_oracle(L):
     assert np.array_equal(muca.muca_host_order(L), oracle.order(L))

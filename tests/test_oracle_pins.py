@@ -523,3 +523,116 @@ def test_sum_of_m4_carries_past_64_bits():
     assert s["SM4"][V] == n * V ** 4 and (n * V ** 4) >> 64 == 5
     assert s["SM2"][V] == n * V * V and s["SA"][V] == n * V and s["SJ"][V] == -3 * V * n
     assert int(job.sm4_hi[V]) == 5 and int(job.sm4_lo[V]) == (n * V ** 4) & (2 ** 64 - 1)
+
+
+# --------------------------------------------------------------------------
+# A job's E_Delta window (the reading that maps a Delta range to [lo, hi])
+# --------------------------------------------------------------------------
+def test_window_tables_confine_and_walls_pull_in():
+    """Moves out of [lo, hi] are rejected whatever the random number; outside
+    the window the walls accept every move towards it, whatever dE_J."""
+    V, beta, lo, hi = 64, 1.0 / 0.9, 20, 40
+    lnW = np.random.default_rng(4).normal(0.0, 1.0, size=V + 1)
+    oracle.OracleJob(4, 0.9, 1, 0, lnW=lnW)  # builds the library
+    job = oracle.OracleJob(4, 0.9, 1, 0, lnW=lnW)
+    job.set_window(lo, hi)
+    kappa = 12 * beta + math.log(2 * V) + 1
+    assert np.allclose(np.diff(job.lnW[hi:]), -kappa) and np.allclose(np.diff(job.lnW[:lo + 1]), kappa)
+    assert np.array_equal(job.lnW[lo:hi + 1], lnW[lo:hi + 1])
+    Bp, Rp, Rm = oracle.tables_window(V, beta, job.lnW, lo, hi)
+    assert Rp[hi] == 0.0 and Rm[lo] == 0.0
+    for dEJ in range(-12, 13):
+        assert not oracle.accept(0, dEJ, +1, hi, Bp, Rp, Rm)      # up from the top edge
+        assert not oracle.accept(0, dEJ, -1, lo, Bp, Rp, Rm)      # down from the bottom edge
+        for E in (hi + 1, hi + 7, V):
+            assert oracle.accept(2 ** 31 - 1, dEJ, -1, E, Bp, Rp, Rm)   # down towards the window
+        for E in (0, lo - 5, lo - 1):
+            assert oracle.accept(2 ** 31 - 1, dEJ, +1, E, Bp, Rp, Rm)   # up towards the window
+    # inside the window the tables are the plain ones
+    B0, P0, M0 = oracle.tables(V, beta, job.lnW)
+    assert np.array_equal(Bp, B0)
+    assert np.array_equal(Rp[lo:hi], P0[lo:hi]) and np.array_equal(Rm[lo + 1:hi + 1], M0[lo + 1:hi + 1])
+
+
+def test_window_stationary_distribution_l2():
+    """Confined to E_Delta in [2, 6], the sweep samples exp(-beta E_J) W(E_Delta)
+    restricted to the window and renormalised (enumeration), and records
+    nothing outside it."""
+    beta, lo, hi = 0.5, 2, 6
+    lnW = np.random.default_rng(12).normal(0.0, 1.0, size=9)
+    job = oracle.OracleJob(2, 1.0 / beta, 16, seed=6, lnW=lnW)
+    job.set_window(lo, hi)
+    job.sweep(50)
+    assert np.all((job.state[:, 1] >= lo) & (job.state[:, 1] <= hi)), "walkers did not enter the window"
+    job.take_hist()
+    job.sweep(20000, record=True)
+    h = job.take_hist()
+    assert h[:lo].sum() == 0 and h[hi + 1:].sum() == 0
+    s = job.bin_sums()
+    assert s["H"] == list(h)
+    a = -beta * l2_exact.EJ + lnW[l2_exact.ED]
+    w = np.exp(a - a.max())
+    p = np.array([w[l2_exact.ED == E].sum() for E in range(9)])
+    p[:lo] = 0.0
+    p[hi + 1:] = 0.0
+    p /= p.sum()
+    assert np.all(np.abs(h / h.sum() - p) < 0.004 + 0.05 * p)
+
+
+@pytest.mark.parametrize("lo,hi", [(30, 70), (90, 125), (0, 20)])
+def test_window_flat_histogram_beta0_closed_form(lo, hi):
+    """At beta = 0 the E_Delta density of states is C(V,E) 2^E; its inverse as
+    weights inside a window gives a flat histogram over that window, and
+    walkers that start outside (random lattices sit near E_Delta = 2V/3 = 83)
+    enter it through the walls."""
+    L = 5
+    V = L ** 3
+    lnW = -np.array([math.log(math.comb(V, E)) + E * math.log(2.0) for E in range(V + 1)])
+    job = oracle.OracleJob(L, float("inf"), 32, seed=21, lnW=lnW)
+    job.set_window(lo, hi)
+    job.sweep(40)
+    assert np.all((job.state[:, 1] >= lo) & (job.state[:, 1] <= hi))
+    job.take_hist()
+    job.sweep(6000)
+    h = job.take_hist()
+    assert h[:lo].sum() == 0 and h[hi + 1:].sum() == 0
+    frac = h[lo:hi + 1] / h.sum()
+    n = hi - lo + 1
+    assert np.all(np.abs(frac - 1.0 / n) < 0.25 / n), frac * n
+
+
+def test_window_recursion_converges_to_restricted_density_of_states():
+    """beta = 0, L = 3, window [6, 20]: the plain recursion from flat weights
+    converges, inside the window, to -ln(C(V,E) 2^E) up to a constant; the
+    walls outside follow the edges."""
+    L, lo, hi = 3, 6, 20
+    V = L ** 3
+    job = oracle.OracleJob(L, float("inf"), 16, seed=8)
+    job.set_window(lo, hi)
+    for _ in range(40):
+        job.sweep(2000)
+        job.update_weights(job.take_hist())
+    exact = -np.array([math.log(math.comb(V, E)) + E * math.log(2.0) for E in range(V + 1)])
+    d = np.diff(job.lnW[lo:hi + 1]) - np.diff(exact[lo:hi + 1])
+    assert np.all(np.abs(d) < 0.12), d
+    kappa = math.log(2 * V) + 1
+    assert np.allclose(np.diff(job.lnW[hi:]), -kappa) and np.allclose(np.diff(job.lnW[:lo + 1]), kappa)
+
+
+@pytest.mark.parametrize("flags", [0, 3])
+def test_full_window_is_no_window(flags):
+    """The window [0, V] changes nothing: same chain, same weights bit for bit."""
+    L, T = 3, 1.4
+    a = oracle.OracleJob(L, T, 6, seed=3)
+    b = oracle.OracleJob(L, T, 6, seed=3)
+    a.set_recursion(flags)
+    b.set_recursion(flags)
+    b.set_window(0, L ** 3)
+    for _ in range(4):
+        a.sweep(30)
+        b.sweep(30)
+        ha, hb = a.take_hist(), b.take_hist()
+        assert np.array_equal(ha, hb)
+        assert a.update_weights(ha) == b.update_weights(hb)
+        assert a.lnW.tobytes() == b.lnW.tobytes()
+    assert np.array_equal(a.spins, b.spins)
