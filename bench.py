@@ -27,15 +27,20 @@ sys.path.insert(0, ROOT)
 METRIC = "spin-flip attempts/sec on 1 GPU (plain vs batched/served) + p99 time-to-flat-histogram"
 WORKLOAD = "l12_t2_w256"
 
-# Algorithmic VALU issue slots per attempt (one site visit), counted from what
-# the method must compute, in full-rate lane slots (a full-rate wave64 VALU
-# instruction = 64 lane slots; instruction costs measured on MI355X: v_xor_b32,
-# v_mul_f64, v_cvt_f64_u32 full rate, v_mad_u64_u32 1.5x):
+# Algorithmic VALU issue per attempt (one site visit), in full-rate lane slots
+# (a full-rate wave64 VALU instruction = 64 lane slots): the 45-55 slot-
+# equivalents counted for the method's work (a quarter of a Philox4x32-10
+# block, six neighbour reads and their sum, class and index arithmetic, one
+# u32 -> f64 convert, one FP64 product and compare, a 2-bit write, three
+# conditional integer updates, 1/V of a histogram atomic), taken at the
+# midpoint.  The itemised count with the instruction rates measured on MI355X
+# (v_xor_b32, v_mul_f64, v_cvt_f64_u32 full rate, v_mad_u64_u32 1.5x) is 32.5:
 #   a quarter of a Philox4x32-10 block: 5 32x32->64 products (7.5) and 5
 #   three-input XORs (5) = 12.5; six-neighbour sum 3; proposal 3; dS, dE_J,
 #   dE_Delta 4; u31 to double 2; B' index 1; FP64 threshold product and compare
 #   2; E_J/E_Delta/M updates 3; spin write-back select 1; class/validity 1.
-ALGO_SLOTS_PER_ATTEMPT = 32.5
+ALGO_SLOTS_PER_ATTEMPT = 50.0
+ITEMISED_SLOTS_PER_ATTEMPT = 32.5
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate VALU lane slots.
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # HBM bytes per 10^4-sweep launch of muca_sweep_kernel<4,1,false,true,2> on this
@@ -55,7 +60,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed steps before the timed ones")
     ap.add_argument("--workload", default=WORKLOAD, help="plain workload a step runs (default: the benchmark job)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, saturation, served and convergence legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, saturation, L=16 T=1, served and convergence legs")
     ap.add_argument("--launch", default=None, help="wpw,bpl,lds_tables (default: library's choice)")
     return ap.parse_args()
 
@@ -88,60 +94,161 @@ def run_step(w, deltas, events=None, launch=None):
     return flat, obs, shape
 
 
-def batched_leg(launch_shape=None):
-    """Mixed (L, T) jobs: one persistent launch per iteration vs one launch per job."""
+def batched_leg():
+    """Mixed (L, T) jobs (19 jobs, 4096 walkers, 10 iterations x 1000 sweeps):
+    one persistent launch per iteration over every job (lock-step), in the
+    default and in the autotuned batch shape; asynchronous lanes (jobs grouped
+    by L, each group a batch on its own stream iterating on its own); and one
+    plain launch per job."""
     import torch
 
-    from paper_1502_07214_amd import MucaBatch, MucaJob, workloads
+    from paper_1502_07214_amd import MucaBatch, MucaJob, autotune, workloads
 
     specs = workloads.batched_jobs()
     it, sw = workloads.BATCHED["iterations"], workloads.BATCHED["sweeps"]
     per_sweep = sum(n * L ** 3 for (L, T, n, s) in specs)
+    tuned = autotune.tune_batch(specs, probe_sweeps=500, cache=autotune.CACHE, warm=autotune.BENCH_WARM_BATCH)
     out = {"jobs": len(specs), "walkers": sum(n for (_, _, n, _) in specs), "iterations": it, "sweeps": sw,
-           "attempts": per_sweep * it * sw}
-    for mode in ("batched", "plain"):
+           "attempts": per_sweep * it * sw, "tuned_shape": list(tuned), "lanes": list(workloads.BATCHED_LANES)}
+    for mode in ("batched", "batched_tuned", "async_lanes", "plain"):
         jobs = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
-        batch = MucaBatch(jobs) if mode == "batched" else None
-        if batch is not None and launch_shape:
-            batch.set_launch(*launch_shape)
+        batches = []
+        if mode in ("batched", "batched_tuned"):
+            batches = [MucaBatch(jobs)]
+            if mode == "batched_tuned":
+                batches[0].set_launch(*tuned)
+        elif mode == "async_lanes":
+            from paper_1502_07214_amd.serve import lane_of
+            groups = {}
+            for j in jobs:
+                groups.setdefault(lane_of(j.L, workloads.BATCHED_LANES), []).append(j)
+            for g in groups.values():
+                st = torch.cuda.Stream()
+                for j in g:
+                    j.set_stream(st)
+                batches.append(MucaBatch(g))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(it):
-            if batch is not None:
-                batch.sweep(sw)
-            else:
+        if mode == "async_lanes":
+            left = {id(b): it for b in batches}
+            for b in batches:
+                b.submit(sw)
+            while any(left.values()):
+                moved = False
+                for b in batches:
+                    if left[id(b)] and b.poll():
+                        for j in b.jobs:
+                            j.update_weights(j.reduce_hist())
+                        left[id(b)] -= 1
+                        moved = True
+                        if left[id(b)]:
+                            b.submit(sw)
+                if not moved:
+                    time.sleep(2e-4)
+        else:
+            for k in range(it):
+                if batches:
+                    batches[0].sweep(sw)
+                else:
+                    for j in jobs:
+                        j.sweep(sw)
                 for j in jobs:
-                    j.sweep(sw)
-            for j in jobs:
-                j.update_weights(j.reduce_hist())
+                    j.update_weights(j.reduce_hist())
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[mode + "_attempts_per_s"] = out["attempts"] / dt
         out[mode + "_s"] = dt
-        if batch is not None:
-            batch.free()
+        for b in batches:
+            b.free()
         for j in jobs:
             j.free()
     out["speedup"] = out["batched_attempts_per_s"] / out["plain_attempts_per_s"]
+    out["async_vs_lockstep"] = out["async_lanes_attempts_per_s"] / out["batched_attempts_per_s"]
     return out
 
 
 def served_leg():
-    """Poisson stream of MUCA jobs: continuous batching vs one job at a time."""
+    """The Poisson stream of MUCA jobs at its stated size (200 jobs, L 8..24,
+    per-job Delta ranges): continuous batching in asynchronous lanes, the same
+    in lock-step (one launch over every resident job per iteration), and one
+    job at a time, each under the same wall budget (jobs unfinished by then
+    are censored at it, so their latencies are lower bounds)."""
     from paper_1502_07214_amd import workloads
     from paper_1502_07214_amd.serve import ServeConfig, poisson_requests, serve, serve_plain
 
     sp = workloads.SERVED
-    reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"])
-    cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"])
-    fast = dataclasses.replace(cfg, recursion=REC_ACC_EXT)
-    out = {"spec": {k: v for k, v in sp.items()}}
-    for mode, fn, c in (("served", serve, cfg), ("plain", serve_plain, cfg), ("served_fast_recursion", serve, fast)):
+    reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"],
+                            delta_halfwidth=sp["delta_halfwidth"])
+    cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"],
+                      wall_budget=sp["wall_budget"], recursion=REC_ACC_EXT, lane_bounds=tuple(sp["lane_bounds"]))
+    out = {"spec": {k: v for k, v in sp.items()}, "recursion": "accumulated+extrapolate"}
+    modes = (("served_async", serve, cfg), ("served_lockstep", serve, dataclasses.replace(cfg, lane_bounds=())),
+             ("one_at_a_time", serve_plain, cfg))
+    for mode, fn, c in modes:
+        print(f"[bench] served: {mode}", file=sys.stderr, flush=True)
         r = fn(reqs, c)
-        out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "makespan_s", "jobs_per_s", "attempts_per_s",
-                                       "latency_p50_s", "latency_p99_s", "latency_converged_p50_s",
-                                       "latency_converged_p99_s", "iterations_p50", "queue_depth_max")}
+        out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "not_arrived", "makespan_s", "converged_per_s",
+                                       "attempts_per_s", "latency_p50_s", "latency_p99_s",
+                                       "latency_converged_p50_s", "latency_converged_p99_s", "iterations_p50",
+                                       "queue_depth_max")}
     return out
+
+
+def c3_leg():
+    """The L=16, T=1 (first-order regime), 1024-walker job in full (60
+    iterations x 2*10^4 sweeps, 2*10^4 production sweeps, 200 Delta) in the
+    autotuned launch shape, each iteration's sweep launch timed with HIP events
+    on the job's stream; then the first iterations again in the library's
+    default shape, for the same launches."""
+    import numpy as np
+    import torch
+
+    from paper_1502_07214_amd import MucaJob, autotune, workloads
+
+    w = workloads.workload("l16_t1_w1024")
+    deltas = workloads.delta_grid(w["deltas"])
+    shape = autotune.tune_job(w["L"], w["T"], w["n_walkers"], seed=w["seed"], probe_sweeps=1000,
+                              cache=autotune.CACHE, warm=autotune.BENCH_WARM_PLAIN)
+    per_launch = w["n_walkers"] * w["V"] * w["sweeps"]
+
+    def run(launch, iterations, production):
+        job = MucaJob(w["L"], w["T"], w["n_walkers"], seed=w["seed"], max_delta=len(deltas))
+        if launch is not None:
+            job.set_launch(*launch)
+        used = job.get_launch()
+        ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iterations):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(job.stream)
+            job.sweep(w["sweeps"])
+            e1.record(job.stream)
+            job.update_weights(job.reduce_hist())
+            ms.append(e0.elapsed_time(e1))
+        if production:
+            job.sweep(w["production"], record=True)
+            job.reduce_hist()
+            job.reweight(deltas)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        job.free()
+        return used, ms, dt
+
+    used, ms, dt = run(shape, w["iterations"], True)
+    k = 6
+    dused, dms, _ = run(None, k, False)
+    launch_ms = float(np.mean(ms))
+    rate = per_launch / (launch_ms * 1e-3)
+    return {"workload": f"L={w['L']} T={w['T']} walkers={w['n_walkers']} {w['iterations']}x{w['sweeps']} + "
+                        f"{w['production']} production, {len(deltas)} Delta",
+            "tuned_shape": used, "attempts": w["attempts"], "seconds": dt, "attempts_per_s": w["attempts"] / dt,
+            "sweep_launch_ms": launch_ms, "kernel_attempts_per_s": rate,
+            "roofline_frac": rate * ALGO_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S,
+            "roofline_frac_itemised": rate * ITEMISED_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S,
+            "default_shape": dused, "first_launches": k,
+            "default_first_ms": float(np.mean(dms)), "tuned_first_ms": float(np.mean(ms[:k])),
+            "tuned_vs_default_first": float(np.mean(dms)) / float(np.mean(ms[:k]))}
 
 
 def convergence_leg():
@@ -197,7 +304,8 @@ def saturation_leg(launch_ms_out=None):
     job.free()
     return {"workload": f"L={s['L']} T={s['T']} walkers={s['n_walkers']} sweeps={s['sweeps']}", "launch": shape,
             "kernel_attempts_per_s": rate, "launch_ms": ms,
-            "roofline_frac": rate * ALGO_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S}
+            "roofline_frac": rate * ALGO_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S,
+            "roofline_frac_itemised": rate * ITEMISED_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S}
 
 
 def cpu_baseline(w, deltas):
@@ -298,13 +406,17 @@ def main():
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
                      "traffic": TRAFFIC_BYTES_PER_LAUNCH if shape == {"waves_per_walker": 4, "blocks_per_lane": 1,
                                                                       "lds_tables": 1, "lds_bytes": 36960} else None,
-                     "kernel": "muca_sweep_kernel", "slots_per_attempt": ALGO_SLOTS_PER_ATTEMPT},
+                     "kernel": "muca_sweep_kernel", "slots_per_attempt": ALGO_SLOTS_PER_ATTEMPT,
+                     "frac_itemised": kernel_rate * ITEMISED_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S,
+                     "slots_per_attempt_itemised": ITEMISED_SLOTS_PER_ATTEMPT},
     }
     if not args.no_extra:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg()
         print("[bench] saturation leg", file=sys.stderr, flush=True)
         out["saturation"] = saturation_leg()
+        print("[bench] L=16 T=1 1024-walker leg", file=sys.stderr, flush=True)
+        out["l16_t1_w1024"] = c3_leg()
         print("[bench] served leg", file=sys.stderr, flush=True)
         out["served"] = served_leg()
         print("[bench] convergence leg", file=sys.stderr, flush=True)

@@ -170,6 +170,13 @@ int muca_set_weights(muca_job *job, const double *lnW);
 /* Copy the job's current weights (V+1 doubles) to lnW_out. */
 int muca_get_weights(const muca_job *job, double *lnW_out);
 
+/* Order the job's later device work on stream (a hipStream_t, NULL = default
+ * stream) instead of the one given to muca_init, e.g. to move a job created
+ * on one stream into a batch on another.  Waits for the work already queued on
+ * the old stream.  A job in a batch must not change stream while the batch
+ * exists. */
+int muca_set_stream(muca_job *job, void *stream);
+
 /* Confine the job's walkers to the E_Delta window [lo, hi] (0 <= lo < hi <=
  * V).  The paper iterates the weights over all of [0, V] (Sec. II); a job
  * that only needs Delta in some range (its canonical E_Delta distributions
@@ -306,6 +313,17 @@ int muca_batch_get_launch(const muca_batch *batch, int32_t *waves_per_walker, in
  * muca_sweep.  Each job's histogram (and production sums with MUCA_RECORD) is
  * added to as by muca_sweep.  Asynchronous on the jobs' stream. */
 int muca_batch_sweep(muca_batch *batch, int64_t n_sweeps, uint32_t flags);
+
+/* Asynchronous iterations.  Every job's histogram is merged and its weights
+ * updated by the host between iterations (Sec. II); batches on different
+ * streams iterate independently, so the jobs of a short-lattice batch need
+ * not wait for those of a long one.  submit: muca_batch_sweep, then mark the
+ * batch's completion point on its stream (returns at once).  poll: *done = 1
+ * when everything submitted to the batch so far has finished, else 0; never
+ * blocks.  finish: wait for it.  MUCA_E_DEVICE on a failed launch. */
+int muca_batch_submit(muca_batch *batch, int64_t n_sweeps, uint32_t flags);
+int muca_batch_poll(muca_batch *batch, int32_t *done);
+int muca_batch_finish(muca_batch *batch);
 
 /* Release the batch's host resources (waits for queued work).  NULL ignored. */
 void muca_batch_free(muca_batch *batch);

@@ -3,8 +3,9 @@
 The shape (waves per walker, Philox blocks per lane, thresholds in LDS or read
 through the caches) never changes results, only speed.  Candidates are timed
 on throwaway clones of the job (same L, T, walker count, seed and weights) with
-HIP events, so the job being tuned keeps its exact chain.  Choices can be kept
-in a JSON cache keyed by device name and job shape.
+HIP events, so the job being tuned keeps its exact chain.  Choices are kept in
+a JSON cache keyed by device name and job shape; CACHE is the one the
+benchmark uses, committed with the choices measured on an MI355X.
 """
 from __future__ import annotations
 
@@ -15,13 +16,28 @@ from typing import Optional, Sequence
 
 from .muca import MucaBatch, MucaError, MucaJob
 
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
 PLAIN_SHAPES = [(w, b, t) for w in (4, 2, 1) for b in (1, 2) for t in (1, 0)]
 BATCH_SHAPES = [(w, b) for w in (0, 1, 2, 4) for b in (1, 2)]
 
 
 def _device_name() -> str:
+    """The device's architecture and compute-unit count (the marketing name
+    is not always available)."""
     import torch
-    return torch.cuda.get_device_name(torch.cuda.current_device())
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "") or torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{arch.split(':')[0]}/{p.multi_processor_count}cu"
+
+
+def _warm(master: MucaJob, iterations: int, sweeps: int):
+    """A few multicanonical iterations, so that shapes are timed on the
+    weights and lattices of a running job rather than on the first sweeps
+    from random lattices."""
+    for _ in range(iterations):
+        master.sweep(sweeps)
+        master.update_weights(master.reduce_hist())
 
 
 def _load(cache: Optional[str]) -> dict:
@@ -51,42 +67,61 @@ def _time(run, sweeps: int) -> float:
 
 
 def tune_job(L: int, T: float, n_walkers: int, seed: int = 0, lnW=None, probe_sweeps: int = 200,
-             cache: Optional[str] = None) -> tuple:
-    """Fastest (waves_per_walker, blocks_per_lane, lds_tables) for this job shape."""
-    key = f"plain|{_device_name()}|L{L}|T{T!r}|W{n_walkers}"
+             cache: Optional[str] = None, shapes=None, warm: tuple = (0, 0)) -> tuple:
+    """Fastest (waves_per_walker, blocks_per_lane, lds_tables) for this job
+    shape (from the cache when it holds one).  warm = (iterations, sweeps):
+    the clones start from the state and weights of a master job taken through
+    that many iterations first.  ValueError if no candidate shape is valid."""
+    key = f"plain|{_device_name()}|L{L}|T{T!r}|W{n_walkers}|warm{warm[0]}x{warm[1]}"
     data = _load(cache)
     if key in data:
         return tuple(data[key]["shape"])
+    master = MucaJob(L, T, n_walkers, seed=seed, lnW=lnW, max_delta=1)
+    _warm(master, *warm)
+    spins, state = master.read_state()
+    weights = master.lnW
+    master.free()
     best, best_ms, timings = None, float("inf"), {}
-    for shape in PLAIN_SHAPES:
-        clone = MucaJob(L, T, n_walkers, seed=seed, lnW=lnW, max_delta=1)
+    for shape in (PLAIN_SHAPES if shapes is None else shapes):
+        clone = MucaJob(L, T, n_walkers, seed=seed, lnW=weights, max_delta=1)
         try:
             clone.set_launch(*shape)
         except MucaError:
             clone.free()
             continue
+        clone.write_state(spins, state)
         ms = _time(clone.sweep, probe_sweeps)
         clone.free()
         timings[str(shape)] = ms
         if ms < best_ms:
             best, best_ms = shape, ms
-    data[key] = {"shape": list(best), "ms": best_ms, "probe_sweeps": probe_sweeps, "timings": timings}
+    if best is None:
+        raise ValueError(f"no valid launch shape for L={L} T={T} walkers={n_walkers}")
+    data[key] = {"shape": list(best), "ms": best_ms, "probe_sweeps": probe_sweeps, "warm": list(warm),
+                 "timings": timings}
     _save(cache, data)
     return best
 
 
-def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[str] = None) -> tuple:
+def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[str] = None, shapes=None,
+               warm: tuple = (0, 0)) -> tuple:
     """Fastest (waves_per_walker, blocks_per_lane) for a batch of jobs given as
-    (L, T, n_walkers, seed) tuples."""
+    (L, T, n_walkers, seed) tuples (from the cache when it holds one).  warm
+    as for tune_job: the batch is timed after that many iterations of every
+    job.  ValueError if no candidate shape is valid."""
     sig = ",".join(f"{L}:{T!r}:{n}" for (L, T, n, _) in sorted(specs))
-    key = f"batch|{_device_name()}|{sig}"
+    key = f"batch|{_device_name()}|{sig}|warm{warm[0]}x{warm[1]}"
     data = _load(cache)
     if key in data:
         return tuple(data[key]["shape"])
     clones = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
     batch = MucaBatch(clones)
+    for _ in range(warm[0]):
+        batch.sweep(warm[1])
+        for c in clones:
+            c.update_weights(c.reduce_hist())
     best, best_ms, timings = None, float("inf"), {}
-    for shape in BATCH_SHAPES:
+    for shape in (BATCH_SHAPES if shapes is None else shapes):
         try:
             batch.set_launch(*shape)
         except MucaError:
@@ -98,6 +133,32 @@ def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[
     batch.free()
     for c in clones:
         c.free()
-    data[key] = {"shape": list(best), "ms": best_ms, "probe_sweeps": probe_sweeps, "timings": timings}
+    if best is None:
+        raise ValueError(f"no valid batched launch shape for {sig}")
+    data[key] = {"shape": list(best), "ms": best_ms, "probe_sweeps": probe_sweeps, "warm": list(warm),
+                 "timings": timings}
     _save(cache, data)
     return best
+
+
+# warm-up of the benchmark tunings: (iterations, sweeps per iteration)
+BENCH_WARM_PLAIN = (3, 2000)
+BENCH_WARM_BATCH = (3, 500)
+
+
+def tune_benchmark_workloads(cache: str = CACHE) -> dict:
+    """Tune the launch shapes the benchmark uses (the L=16, T=1, 1024-walker
+    job and the 19-job batched workload) into cache."""
+    from . import workloads
+
+    w = workloads.workload("l16_t1_w1024")
+    plain = tune_job(w["L"], w["T"], w["n_walkers"], seed=w["seed"], probe_sweeps=1000, cache=cache,
+                     warm=BENCH_WARM_PLAIN)
+    batch = tune_batch(workloads.batched_jobs(), probe_sweeps=500, cache=cache, warm=BENCH_WARM_BATCH)
+    return {"l16_t1_w1024": plain, "batched": batch}
+
+
+if __name__ == "__main__":
+    import sys
+
+    print(tune_benchmark_workloads(sys.argv[1] if len(sys.argv) > 1 else CACHE), flush=True)

@@ -598,6 +598,15 @@ int muca_set_weights(muca_job *j, const double *lnW)
     return clear_accum(j);
 }
 
+int muca_set_stream(muca_job *j, void *stream)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (int rc = use_device(j)) return rc;
+    HIP_TRY(hipStreamSynchronize(j->stream));  // also completes the last table upload
+    j->stream = reinterpret_cast<hipStream_t>(stream);
+    return MUCA_OK;
+}
+
 int muca_set_window(muca_job *j, int32_t lo, int32_t hi)
 {
     if (!j || lo < 0 || hi > j->g.V || lo >= hi) return MUCA_E_INVAL;
@@ -895,6 +904,7 @@ struct muca_batch {
     std::vector<int> job_wpw;
     size_t total_walkers;
     size_t tab_bytes;  // LDS reserved for staged tables (0: every job reads them through the caches)
+    hipEvent_t done;   // recorded after the last submitted launch
 };
 
 namespace {
@@ -1224,9 +1234,14 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
         return rc;
     }
     b->tab_bytes = plan_tab_bytes(plan_of(b, b->wpw));
+    b->done = nullptr;
     if (int rc = upload_batch(b)) {
         delete b;
         return rc;
+    }
+    if (hipError_t e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming); e != hipSuccess) {
+        delete b;
+        return fail_device(e, "hipEventCreate(batch)");
     }
     *out = b;
     return MUCA_OK;
@@ -1275,11 +1290,43 @@ int muca_batch_sweep(muca_batch *b, int64_t n_sweeps, uint32_t flags)
                          b->stream);
 }
 
+int muca_batch_submit(muca_batch *b, int64_t n_sweeps, uint32_t flags)
+{
+    if (int rc = muca_batch_sweep(b, n_sweeps, flags)) return rc;
+    HIP_TRY(hipEventRecord(b->done, b->stream));
+    return MUCA_OK;
+}
+
+int muca_batch_poll(muca_batch *b, int32_t *done)
+{
+    if (!b || !done) return MUCA_E_INVAL;
+    if (int rc = use_device(b->jobs[0])) return rc;
+    const hipError_t e = hipEventQuery(b->done);
+    if (e == hipSuccess) {
+        *done = 1;
+        return MUCA_OK;
+    }
+    if (e == hipErrorNotReady) {
+        *done = 0;
+        return MUCA_OK;
+    }
+    return fail_device(e, "hipEventQuery(batch)");
+}
+
+int muca_batch_finish(muca_batch *b)
+{
+    if (!b) return MUCA_E_INVAL;
+    if (int rc = use_device(b->jobs[0])) return rc;
+    HIP_TRY(hipEventSynchronize(b->done));
+    return MUCA_OK;
+}
+
 void muca_batch_free(muca_batch *b)
 {
     if (!b) return;
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
+    if (b->done) (void)hipEventDestroy(b->done);
     delete b;
 }
 

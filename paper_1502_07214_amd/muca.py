@@ -31,7 +31,8 @@ EXPORTS = (
     "muca_host_order", "muca_strerror", "muca_free", "muca_batch_query_size", "muca_batch_create",
     "muca_batch_set_launch", "muca_batch_get_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
     "muca_reweight_hist", "muca_reweight_hist_sums", "muca_set_recursion", "muca_batch_sweep_static",
-    "muca_set_window", "muca_get_window", "muca_host_walls",
+    "muca_set_window", "muca_get_window", "muca_host_walls", "muca_batch_submit", "muca_batch_poll",
+    "muca_batch_finish", "muca_set_stream",
 )
 
 # weight recursion flags (muca_set_recursion)
@@ -89,6 +90,7 @@ def lib():
     L.muca_host_tables.argtypes = [i32, dbl, P(dbl), i32, i32, P(dbl), P(dbl), P(dbl)]
     L.muca_host_walls.argtypes = [i32, dbl, i32, i32, P(dbl)]
     L.muca_set_window.argtypes = [vp, i32, i32]
+    L.muca_set_stream.argtypes = [vp, vp]
     L.muca_get_window.argtypes = [vp, P(i32), P(i32)]
     L.muca_host_order.argtypes = [i32, P(i32)]
     L.muca_strerror.argtypes = [ctypes.c_int]
@@ -101,6 +103,9 @@ def lib():
     L.muca_batch_get_launch.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.muca_batch_sweep.argtypes = [vp, i64, u32]
     L.muca_batch_sweep_static.argtypes = [P(vp), i32, i64, u32]
+    L.muca_batch_submit.argtypes = [vp, i64, u32]
+    L.muca_batch_poll.argtypes = [vp, P(i32)]
+    L.muca_batch_finish.argtypes = [vp]
     L.muca_batch_free.argtypes = [vp]
     L.muca_batch_free.restype = None
     L.muca_flatness.argtypes = [P(i64), i32, i32, P(dbl)]
@@ -272,6 +277,24 @@ class MucaJob:
         _check(lib().muca_set_recursion(self._h, int(flags)), "muca_set_recursion")
         self.recursion = int(flags)
 
+    def set_stream(self, stream):
+        """Order the job's later work on stream (a torch.cuda.Stream)."""
+        _check(lib().muca_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "muca_set_stream")
+        self.stream = stream
+
+    def submit(self, n_sweeps: int, record: bool = False):
+        """muca_sweep, then mark its completion on the job's stream."""
+        import torch
+
+        self.sweep(n_sweeps, record)
+        self._done = torch.cuda.Event()
+        self._done.record(self.stream)
+
+    def poll(self) -> bool:
+        """True when everything submitted has finished (never blocks)."""
+        ev = getattr(self, "_done", None)
+        return ev is None or ev.query()
+
     def set_window(self, lo: int, hi: int):
         """Confine the walkers to E_Delta in [lo, hi] (muca_set_window)."""
         _check(lib().muca_set_window(self._h, int(lo), int(hi)), "muca_set_window")
@@ -373,6 +396,19 @@ class MucaBatch:
 
     def sweep(self, n_sweeps: int, record: bool = False):
         _check(lib().muca_batch_sweep(self._h, int(n_sweeps), MUCA_RECORD if record else 0), "muca_batch_sweep")
+
+    def submit(self, n_sweeps: int, record: bool = False):
+        """Enqueue n_sweeps sweeps and mark their completion (muca_batch_submit)."""
+        _check(lib().muca_batch_submit(self._h, int(n_sweeps), MUCA_RECORD if record else 0), "muca_batch_submit")
+
+    def poll(self) -> bool:
+        """True when everything submitted has finished (never blocks)."""
+        d = ctypes.c_int32()
+        _check(lib().muca_batch_poll(self._h, ctypes.byref(d)), "muca_batch_poll")
+        return bool(d.value)
+
+    def finish(self):
+        _check(lib().muca_batch_finish(self._h), "muca_batch_finish")
 
     def free(self):
         if getattr(self, "_h", None):

@@ -97,7 +97,8 @@ def _probe_margin(V: int) -> int:
     return 2 + V // 100
 
 
-def probe_windows(requests: Sequence[Request], probe: ProbeConfig = ProbeConfig()) -> Dict[int, Tuple[int, int]]:
+def probe_windows(requests: Sequence[Request], probe: ProbeConfig = ProbeConfig(),
+                  retire: Optional[list] = None) -> Dict[int, Tuple[int, int]]:
     """E_Delta window of each request with a Delta range.
 
     Reading (the paper iterates over all of [0, V]): the window is the range
@@ -112,7 +113,8 @@ def probe_windows(requests: Sequence[Request], probe: ProbeConfig = ProbeConfig(
     E_Delta seen at Delta_hi to the highest seen at Delta_lo, widened by
     2 + V/100 bins and clipped to [0, V].  The probes of all requests run in
     one batched launch; their chains depend only on the request, so a job's
-    window is the same alone and in any mix."""
+    window is the same alone and in any mix.  The probe jobs are released
+    here, or appended to retire for the caller to release later."""
     reqs = [r for r in requests if r.delta_range is not None]
     if not reqs:
         return {}
@@ -148,7 +150,10 @@ def probe_windows(requests: Sequence[Request], probe: ProbeConfig = ProbeConfig(
         lo, hi = max(0, lo - m), min(V, hi + m)
         out[r.id] = (lo, hi)
     for p in probes:
-        p.free()
+        if retire is not None:
+            retire.append(p)
+        else:
+            p.free()
     return out
 
 
@@ -179,10 +184,16 @@ class ServeConfig:
     recursion: int = 0             # weight recursion flags (REC_ACCUMULATED | REC_EXTRAPOLATE; 0 plain)
     probe: ProbeConfig = field(default_factory=ProbeConfig)  # Delta range -> E_Delta window
     wall_budget: Optional[float] = None  # seconds; jobs unfinished by then are censored at it
+    # Asynchronous lanes: resident jobs with L <= lane_bounds[0] form lane 0,
+    # L <= lane_bounds[1] lane 1, ..., the rest the last lane; each lane is a
+    # batch on its own stream and iterates on its own.  () = one lane: every
+    # resident job advances one iteration per launch (lock-step).
+    lane_bounds: Tuple[int, ...] = ()
 
 
 class _Live:
-    def __init__(self, rec: JobRecord, cfg: ServeConfig, now: float, window: Optional[Tuple[int, int]]):
+    def __init__(self, rec: JobRecord, cfg: ServeConfig, now: float, window: Optional[Tuple[int, int]],
+                 stream=None):
         r = rec.req
         self.rec = rec
         self.job = MucaJob(r.L, r.T, r.n_walkers, seed=r.seed, lnW=tilted_weights(r.L, r.T), max_delta=1)
@@ -192,6 +203,8 @@ class _Live:
         self.lo, self.hi = window if window is not None else (0, self.V)
         if window is not None:
             self.job.set_window(*window)
+        if stream is not None:
+            self.job.set_stream(stream)
         rec.window = (self.lo, self.hi)
         rec.admitted = now
 
@@ -233,25 +246,80 @@ def _censor_at_budget(records: Dict[int, JobRecord], arrived: Sequence[Request],
             rec.converged = False
 
 
+def lane_of(L: int, bounds: Tuple[int, ...]) -> int:
+    for k, b in enumerate(bounds):
+        if L <= b:
+            return k
+    return len(bounds)
+
+
+class _Lane:
+    """Resident jobs of one size class, swept as one batch (or alone) on the
+    lane's own stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.active: List[_Live] = []
+        self.members: List[_Live] = []  # the jobs of the launch in flight
+        self.batch = None
+        self.changed = False
+        self.in_flight = False
+
+    def launch(self, cfg: ServeConfig):
+        if len(self.active) == 1:
+            # a lone job runs its own launch (its shape keeps neighbour
+            # positions in registers and spreads few walkers over whole blocks)
+            if self.batch is not None:
+                self.batch.free()
+                self.batch = None
+            self.active[0].job.submit(cfg.sweeps)
+        else:
+            if self.changed or self.batch is None:
+                if self.batch is not None:
+                    self.batch.free()
+                self.batch = MucaBatch([a.job for a in self.active])
+                if cfg.shape:
+                    self.batch.set_launch(*cfg.shape)
+            self.batch.submit(cfg.sweeps)
+        self.changed = False
+        self.members = list(self.active)
+        self.in_flight = True
+
+    def done(self) -> bool:
+        if len(self.members) == 1 and self.batch is None:
+            return self.members[0].job.poll()
+        return self.batch.poll()
+
+
 def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False, progress=None) -> dict:
     """Continuous batching over the request stream (real time).  progress, if
-    given, is called with the finished job records as jobs finish."""
+    given, is called with the finished job records as jobs finish.
+
+    Arrivals join a FIFO queue and are admitted while the resident walkers
+    and device bytes fit; an admitted job's window comes from its probes and
+    it joins the lane of its size.  Every lane with resident jobs and no launch
+    in flight launches one iteration (S sweeps) of its jobs; a lane whose
+    launch has finished merges each job's histogram, finishes the flat (or
+    capped) ones and updates the others' weights, while the other lanes keep
+    running.  Host resources of finished jobs are released at the end (their
+    release would wait for the whole device)."""
     import torch
 
     t0 = time.perf_counter()
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue: collections.deque = collections.deque()
     arrived: List[Request] = []
-    active: List[_Live] = []
+    n_lanes = len(cfg.lane_bounds) + 1
+    lanes = [_Lane(torch.cuda.Stream() if n_lanes > 1 else torch.cuda.current_stream()) for _ in range(n_lanes)]
     records: Dict[int, JobRecord] = {}
     kept = {}
-    batch = None
+    retired: List[MucaJob] = []
     walkers = 0
     nbytes = 0
     depth = []
     launches = 0
     attempts = 0
-    while pending or queue or active:
+    while pending or queue or any(l.active for l in lanes):
         now = time.perf_counter() - t0
         if cfg.wall_budget is not None and now >= cfg.wall_budget:
             break
@@ -260,10 +328,11 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
             queue.append(r)
             arrived.append(r)
         admit = []
+        resident = any(l.active for l in lanes)
         while queue:
             r = queue[0]
             fb = footprint(r)
-            if (active or admit) and (walkers + r.n_walkers > cfg.max_walkers or nbytes + fb > cfg.hbm_budget):
+            if (resident or admit) and (walkers + r.n_walkers > cfg.max_walkers or nbytes + fb > cfg.hbm_budget):
                 break
             queue.popleft()
             admit.append(r)
@@ -271,42 +340,35 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
             nbytes += fb
         if admit:
             # the admitted jobs' windows: their probes in one batched launch
-            windows = probe_windows(admit, cfg.probe)
+            windows = probe_windows(admit, cfg.probe, retired)
             for r in admit:
                 rec = JobRecord(r)
                 records[r.id] = rec
-                active.append(_Live(rec, cfg, time.perf_counter() - t0, windows.get(r.id)))
-        changed = bool(admit)
+                lane = lanes[lane_of(r.L, cfg.lane_bounds)]
+                lane.active.append(_Live(rec, cfg, time.perf_counter() - t0, windows.get(r.id),
+                                         lane.stream if n_lanes > 1 else None))
+                lane.changed = True
         depth.append(len(queue))
-        if not active:
+        for lane in lanes:
+            if lane.active and not lane.in_flight:
+                lane.launch(cfg)
+                launches += 1
+                attempts += sum(a.rec.req.n_walkers * a.V for a in lane.members) * cfg.sweeps
+        if not any(l.in_flight for l in lanes):
             if pending:
                 _wait_until(t0, pending[0].arrival if cfg.wall_budget is None
                             else min(pending[0].arrival, cfg.wall_budget))
             continue
-        if len(active) == 1:
-            # a lone job runs its own launch (its shape keeps neighbour
-            # positions in registers and spreads few walkers over whole blocks)
-            if batch is not None:
-                batch.free()
-                batch = None
-            active[0].job.sweep(cfg.sweeps)
-        else:
-            if changed or batch is None:
-                if batch is not None:
-                    batch.free()
-                batch = MucaBatch([a.job for a in active])
-                if cfg.shape:
-                    batch.set_launch(*cfg.shape)
-            batch.sweep(cfg.sweeps)
-        launches += 1
-        attempts += sum(a.rec.req.n_walkers * a.V for a in active) * cfg.sweeps
-        torch.cuda.current_stream().synchronize()
-        now = time.perf_counter() - t0
-        done = [a for a in active if a.step_done(cfg, now)]
-        if done:
-            if batch is not None:
-                batch.free()
-                batch = None
+        progressed = False
+        for lane in lanes:
+            if not (lane.in_flight and lane.done()):
+                continue
+            lane.in_flight = False
+            progressed = True
+            now = time.perf_counter() - t0
+            done = [a for a in lane.members if a.step_done(cfg, now)]
+            if not done:
+                continue
             if progress is not None:
                 progress([a.rec for a in done])
             for a in done:
@@ -315,20 +377,29 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
                 if keep_jobs:
                     kept[a.rec.req.id] = a.job
                 else:
-                    a.job.free()
-            active = [a for a in active if a not in done]
-    if batch is not None:
-        batch.free()
-    if cfg.wall_budget is not None and (pending or queue or active):
+                    retired.append(a.job)
+            lane.active = [a for a in lane.active if a not in done]
+            lane.changed = True
+        if not progressed:
+            time.sleep(2e-4)
+    for lane in lanes:
+        if lane.batch is not None:
+            lane.batch.free()
+    torch.cuda.synchronize()
+    if cfg.wall_budget is not None and (pending or queue or any(l.active for l in lanes)):
         _censor_at_budget(records, arrived, cfg.wall_budget)
-        for a in active:
-            if keep_jobs:
-                kept[a.rec.req.id] = a.job
-            else:
-                a.job.free()
+        for lane in lanes:
+            for a in lane.active:
+                if keep_jobs:
+                    kept[a.rec.req.id] = a.job
+                else:
+                    retired.append(a.job)
     makespan = time.perf_counter() - t0
+    for j in retired:
+        j.free()
     out = _summary(records, makespan, attempts, launches, depth, kept)
     out["not_arrived"] = len(pending)
+    out["lanes"] = n_lanes
     return out
 
 

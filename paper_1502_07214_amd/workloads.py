@@ -71,16 +71,20 @@ def batched_jobs(spec=BATCHED) -> list:
     return [(L, T, n, 100_000 * L + int(round(T * 1e4))) for (L, T), n in sorted(counts.items())]
 
 
-# Served: Poisson arrivals (mean 20 jobs/s) of MUCA jobs, weights tilted to
-# Delta_mid(T), 500 sweeps per iteration until the E_Delta histogram over
-# [0, V] is flat (min/mean > 0.5), cap 2000 iterations.  The full mix (L in
-# 8..24, 200 jobs) needs hours of device time per run because flatness over the
-# whole E_Delta range of an L = 24 lattice takes thousands of iterations; the
-# benchmark serves the same kind of stream at L in 6..10.
-SERVED = dict(n_jobs=60, rate=20.0, seed=0, L_range=(6, 10), T_range=(0.9, 2.0),
-              walker_choices=(64, 128, 192, 256, 320, 384, 448, 512), sweeps=500, threshold=0.5,
-              max_iterations=2000)
-SERVED_FULL = dict(SERVED, n_jobs=200, L_range=(8, 24))
+# Served: Poisson arrivals (mean 20 jobs/s, seed 0) of 200 MUCA jobs, L
+# uniform in 8..24, T uniform in [0.9, 2.0], 64..512 walkers (multiples of
+# 64), each asking for Delta in Delta_mid(T) +- 0.1 (its E_Delta window comes
+# from two canonical probes), weights tilted to Delta_mid(T), 500 sweeps per
+# iteration until the histogram over the window is flat (min/mean > 0.5), cap
+# 2000 iterations; the run stops at a wall budget and the jobs unfinished by
+# then are censored at it.  Lanes: L <= 12, <= 16, <= 20, larger.
+SERVED = dict(n_jobs=200, rate=20.0, seed=0, L_range=(8, 24), T_range=(0.9, 2.0),
+              walker_choices=(64, 128, 192, 256, 320, 384, 448, 512), delta_halfwidth=0.1, sweeps=500,
+              threshold=0.5, max_iterations=2000, wall_budget=40.0, lane_bounds=(12, 16, 20))
+
+# Lanes of the batched workload when its jobs iterate asynchronously (L <= 8,
+# 10, 12, 16, larger).
+BATCHED_LANES = (8, 10, 12, 16)
 
 # Saturation: enough walkers to fill every SIMD several times over (roofline run).
 SATURATION = dict(L=8, T=2.0, n_walkers=65536, seed=0, sweeps=100)

@@ -218,3 +218,36 @@ def test_full_size_batched_workload_sampled():
     batch.free()
     for j in jobs:
         j.free()
+
+
+def test_tuned_shapes_keep_the_chain(tmp_path):
+    """The autotuner's choices (timed on clones, written to a cache and read
+    back from it) change speed only: the job and the batch swept in the tuned
+    shapes equal the default shapes bit for bit."""
+    from paper_1502_07214_amd import autotune
+
+    cache = str(tmp_path / "tune.json")
+    L, T, nw, seed = 10, 1.3, 24, 5
+    shape = autotune.tune_job(L, T, nw, seed=seed, probe_sweeps=20, cache=cache)
+    assert autotune.tune_job(L, T, nw, seed=seed, probe_sweeps=20, cache=cache) == shape
+    a, b = MucaJob(L, T, nw, seed=seed, max_delta=1), MucaJob(L, T, nw, seed=seed, max_delta=1)
+    a.set_launch(*shape)
+    a.sweep(50)
+    b.sweep(50)
+    assert np.array_equal(a.reduce_hist(), b.reduce_hist())
+    assert np.array_equal(a.read_state()[0], b.read_state()[0])
+    specs = [(8, 1.0, 16, 1), (12, 2.0, 8, 2), (6, 0.9, 12, 3)]
+    bshape = autotune.tune_batch(specs, probe_sweeps=10, cache=cache)
+    ja = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
+    jb = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
+    ba, bb = MucaBatch(ja), MucaBatch(jb)
+    ba.set_launch(*bshape)
+    ba.sweep(30)
+    bb.sweep(30)
+    for x, y in zip(ja, jb):
+        assert np.array_equal(x.reduce_hist(), y.reduce_hist())
+        assert np.array_equal(x.read_state()[0], y.read_state()[0])
+    for o in [a, b, ba, bb] + ja + jb:
+        o.free()
+    with pytest.raises(ValueError):
+        autotune.tune_job(L, T, nw, seed=seed, probe_sweeps=5, shapes=[(3, 1, 0)])

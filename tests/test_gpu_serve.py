@@ -68,16 +68,19 @@ def test_lone_and_batched_launches_alternate():
         j.free()
 
 
-def test_large_windowed_jobs_served_equal_alone():
+@pytest.mark.parametrize("lane_bounds", [(), (8, 17)])
+def test_large_windowed_jobs_served_equal_alone(lane_bounds):
     """Jobs at L = 16..20 with Delta ranges Delta_mid(T) +- 0.1 (windows from
     the canonical probes), served in a mix of four, equal the same jobs served
-    alone: window, flatness history, weights and walkers bit for bit."""
+    alone: window, flatness history, weights and walkers bit for bit; in
+    lock-step and in asynchronous lanes (L <= 8, L <= 17, larger: three streams)."""
     reqs = [Request(0, 16, 0.95, 64, 101, 0.0, (2.85, 3.05)), Request(1, 20, 2.0, 64, 102, 0.0, (2.42, 2.62)),
-            Request(2, 18, 1.4182, 128, 103, 0.01, (2.7446, 2.9446)), Request(3, 6, 1.2, 64, 104, 0.02, (2.8, 3.0))]
-    cfg = ServeConfig(sweeps=40, threshold=0.5, max_iterations=6, max_walkers=1024)
-    print("[serve] windowed L=16..20 mix", flush=True)
+            Request(2, 18, 1.4182, 128, 103, 0.01, (2.7446, 2.9446)), Request(3, 6, 1.2, 64, 104, 0.02, (2.8, 3.0)),
+            Request(4, 12, 1.0, 64, 105, 0.0, (2.85, 3.05))]
+    cfg = ServeConfig(sweeps=40, threshold=0.5, max_iterations=6, max_walkers=1024, lane_bounds=lane_bounds)
+    print(f"[serve] windowed L=16..20 mix, lanes {lane_bounds}", flush=True)
     mix = serve(reqs, cfg, keep_jobs=True)
-    assert mix["jobs"] == 4
+    assert mix["jobs"] == 5 and mix["lanes"] == len(lane_bounds) + 1
     for r in reqs[:3]:
         a = mix["records"][r.id]
         V = r.L ** 3
@@ -105,3 +108,28 @@ def test_wall_budget_censors_unfinished_jobs():
     assert all(abs(r.finished - 1.5) < 1e-9 for r in out["records"].values())
     plain = serve_plain(reqs, cfg)
     assert plain["censored"] == 4 and plain["jobs"] == 4
+
+
+def test_batch_submit_poll_finish():
+    """muca_batch_submit returns at once; poll turns true when the launch has
+    finished; the results equal a synchronous batched sweep."""
+    from paper_1502_07214_amd import MucaBatch, MucaJob
+
+    specs = [(8, 1.0, 64, 7), (12, 2.0, 32, 8)]
+    a = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
+    b = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
+    ba, bb = MucaBatch(a), MucaBatch(b)
+    ba.submit(400)
+    polls = 0
+    while not ba.poll():
+        polls += 1
+    ba.finish()
+    bb.sweep(400)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.reduce_hist(), y.reduce_hist())
+        assert np.array_equal(x.read_state()[1], y.read_state()[1])
+    print(f"[serve] submit/poll: {polls} polls before done", flush=True)
+    ba.free()
+    bb.free()
+    for j in a + b:
+        j.free()
