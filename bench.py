@@ -405,7 +405,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
                      "traffic": TRAFFIC_BYTES_PER_LAUNCH if shape == {"waves_per_walker": 4, "blocks_per_lane": 1,
-                                                                      "lds_tables": 1, "lds_bytes": 36960} else None,
+                                                                      "lds_tables": 1, "packed": 0,
+                                                                      "lds_bytes": 36960} else None,
                      "kernel": "muca_sweep_kernel", "slots_per_attempt": ALGO_SLOTS_PER_ATTEMPT,
                      "frac_itemised": kernel_rate * ITEMISED_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S,
                      "slots_per_attempt_itemised": ITEMISED_SLOTS_PER_ATTEMPT},

@@ -251,13 +251,20 @@ int muca_reset_accum(muca_job *job);
  * waves_per_walker in {1, 2, 4} (64, 128 or 256 lanes cooperate on one walker),
  * blocks_per_lane in {1, 2} (4 or 8 consecutive sites per lane per pass),
  * lds_tables: 1 = thresholds and neighbour table in LDS, 0 = read through the
- * caches, -1 = automatic.  MUCA_E_SIZE if the shape needs more LDS than a CU has. */
+ * caches, -1 = automatic; packing: 1 = lattices held in LDS as 2-bit codes (a
+ * quarter of the bytes, one more field extract per neighbour read; needs
+ * blocks_per_lane 1), 0 = one byte per site, -1 = automatic (packed when that
+ * raises the blocks resident on a compute unit).  The histogram of the
+ * iteration is kept in LDS unless that lowers the resident blocks.
+ * MUCA_E_INVAL on a bad value, MUCA_E_SIZE if the shape needs more LDS than a
+ * block may use. */
 int muca_set_launch(muca_job *job, int32_t waves_per_walker, int32_t blocks_per_lane,
-                    int32_t lds_tables);
+                    int32_t lds_tables, int32_t packing);
 
-/* Current launch shape and its LDS bytes per block. */
+/* Current launch shape (packing as resolved: 0 or 1) and its LDS bytes per
+ * block.  Any pointer may be NULL. */
 int muca_get_launch(const muca_job *job, int32_t *waves_per_walker, int32_t *blocks_per_lane,
-                    int32_t *lds_tables, int32_t *lds_bytes);
+                    int32_t *lds_tables, int32_t *packing, int32_t *lds_bytes);
 
 /* Diagnostics: when enabled, the sweep kernel counts passes (colour-class
  * groups of sites handled together), rounds of the exact E_Delta resolution,
@@ -291,22 +298,24 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
 
 /* Launch shape of the batched kernel (results do not depend on it):
  * waves_per_walker in {0, 1, 2, 4}, blocks_per_lane in {1, 2}; blocks <= 0
- * fills the device (occupancy query).  The default is one wave per walker for
- * every job (two or four when four lattices of the largest job do not fit in
- * the LDS of a block).  waves_per_walker 0 picks per job: four waves per walker for the
- * jobs whose walkers would otherwise set the length of the launch (large
- * lattices, few waves in the batch), one for the rest; it pays while the
- * weights are smooth.  MUCA_E_SIZE if the lattice slots of the largest tile
- * do not fit in LDS. */
+ * fills the device (occupancy query); packing as for muca_set_launch.  The
+ * default is one wave per walker for every job (two or four when four
+ * lattices of the largest job do not fit in the LDS of a block even packed)
+ * and automatic packing.  waves_per_walker 0 picks per job: four waves per
+ * walker for the jobs whose walkers would otherwise set the length of the
+ * launch (large lattices, few waves in the batch), one for the rest; it pays
+ * while the weights are smooth.  MUCA_E_SIZE if the lattice slots of the
+ * largest tile do not fit in LDS. */
 int muca_batch_set_launch(muca_batch *batch, int32_t waves_per_walker, int32_t blocks_per_lane,
-                          int32_t blocks);
+                          int32_t blocks, int32_t packing);
 
 /* The launch shape in use: the waves per walker of each job's tiles
  * (waves_per_walker[k] for the k-th job passed to muca_batch_create, so an
- * array of n_jobs), the Philox blocks per lane and the LDS bytes per block.
- * Any pointer may be NULL.  MUCA_E_INVAL for a NULL batch. */
+ * array of n_jobs), the Philox blocks per lane, the packing (0 or 1) and the
+ * LDS bytes per block.  Any pointer may be NULL.  MUCA_E_INVAL for a NULL
+ * batch. */
 int muca_batch_get_launch(const muca_batch *batch, int32_t *waves_per_walker, int32_t *blocks_per_lane,
-                          int32_t *lds_bytes);
+                          int32_t *packing, int32_t *lds_bytes);
 
 /* n_sweeps (0..MUCA_MAX_SWEEPS_PER_CALL) sweeps of every walker of every job in
  * the batch, in one persistent launch per at most 2^26 sweeps; flags as for

@@ -18,8 +18,10 @@ from .muca import MucaBatch, MucaError, MucaJob
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-PLAIN_SHAPES = [(w, b, t) for w in (4, 2, 1) for b in (1, 2) for t in (1, 0)]
-BATCH_SHAPES = [(w, b) for w in (0, 1, 2, 4) for b in (1, 2)]
+# (waves per walker, Philox blocks per lane, thresholds in LDS, packed lattices)
+PLAIN_SHAPES = [(w, b, t, p) for w in (4, 2, 1) for b in (1, 2) for t in (1, 0) for p in (0, 1) if b == 1 or p == 0]
+# (waves per walker, Philox blocks per lane, persistent blocks (0: fill), packed lattices)
+BATCH_SHAPES = [(w, b, 0, p) for w in (0, 1, 2, 4) for b in (1, 2) for p in (0, 1) if b == 1 or p == 0]
 
 
 def _device_name() -> str:
@@ -68,11 +70,11 @@ def _time(run, sweeps: int) -> float:
 
 def tune_job(L: int, T: float, n_walkers: int, seed: int = 0, lnW=None, probe_sweeps: int = 200,
              cache: Optional[str] = None, shapes=None, warm: tuple = (0, 0)) -> tuple:
-    """Fastest (waves_per_walker, blocks_per_lane, lds_tables) for this job
-    shape (from the cache when it holds one).  warm = (iterations, sweeps):
+    """Fastest (waves_per_walker, blocks_per_lane, lds_tables, packing) for
+    this job shape (from the cache when it holds one).  warm = (iterations, sweeps):
     the clones start from the state and weights of a master job taken through
     that many iterations first.  ValueError if no candidate shape is valid."""
-    key = f"plain|{_device_name()}|L{L}|T{T!r}|W{n_walkers}|warm{warm[0]}x{warm[1]}"
+    key = f"plain2|{_device_name()}|L{L}|T{T!r}|W{n_walkers}|warm{warm[0]}x{warm[1]}"
     data = _load(cache)
     if key in data:
         return tuple(data[key]["shape"])
@@ -105,12 +107,13 @@ def tune_job(L: int, T: float, n_walkers: int, seed: int = 0, lnW=None, probe_sw
 
 def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[str] = None, shapes=None,
                warm: tuple = (0, 0)) -> tuple:
-    """Fastest (waves_per_walker, blocks_per_lane) for a batch of jobs given as
-    (L, T, n_walkers, seed) tuples (from the cache when it holds one).  warm
+    """Fastest (waves_per_walker, blocks_per_lane, blocks, packing) for a batch
+    of jobs given as (L, T, n_walkers, seed) tuples (from the cache when it
+    holds one).  warm
     as for tune_job: the batch is timed after that many iterations of every
     job.  ValueError if no candidate shape is valid."""
     sig = ",".join(f"{L}:{T!r}:{n}" for (L, T, n, _) in sorted(specs))
-    key = f"batch|{_device_name()}|{sig}|warm{warm[0]}x{warm[1]}"
+    key = f"batch2|{_device_name()}|{sig}|warm{warm[0]}x{warm[1]}"
     data = _load(cache)
     if key in data:
         return tuple(data[key]["shape"])

@@ -97,7 +97,8 @@ Layout make_layout(const muca_params *p)
     g.off_r = 256;
     g.off_lnw = g.off_r + align_up(16 * (V1 + 2 * kRPad), 256);
     g.off_nb = g.off_lnw + align_up(8 * V1, 256);
-    g.off_site = g.off_nb + align_up((size_t)12 * g.Vp, 256);
+    g.off_nb2 = g.off_nb + align_up((size_t)12 * g.Vp, 256);
+    g.off_site = g.off_nb2 + align_up((size_t)12 * g.Vp, 256);
     g.tables_bytes = g.off_site + align_up((size_t)2 * g.Vp, 256);
     g.accum_bytes = align_up(7 * 8 * V1, 256);
     g.off_obs_lnp = align_up((size_t)g.max_delta * (1 + MUCA_N_OBS) * 8, 256);
@@ -153,7 +154,8 @@ struct muca_job {
     double beta;
     uint32_t k0, k1;
     int device;
-    int max_lds;
+    int max_lds;  // LDS bytes a block may use
+    int lds_cu;   // LDS bytes of one compute unit
     int n_cu;
     hipStream_t stream;
     muca_dev_buffers d;
@@ -167,7 +169,7 @@ struct muca_job {
     // E_Delta window [win_lo, win_hi] the walkers are confined to ([0, V]: none)
     int win_lo, win_hi;
     // launch shape
-    int wpw, bpl, lds_tables_req;
+    int wpw, bpl, lds_tables_req, pack_req;
     // pinned staging
     unsigned char *pin_tables;  // Bp | R | lnW regions of the tables buffer
     unsigned char *pin_hist;    // hist + error word
@@ -207,21 +209,32 @@ int cached_passes(const Layout &g, int wpw, int bpl, SweepArgs *a)
 }
 
 struct LaunchPlan {
-    bool lds_tables, lds_hist;
+    bool lds_tables, lds_hist, pack;
     size_t lds;
     int off_hist, off_lat, off_r, off_nb;
 };
 
-bool plan_launch(const muca_job *j, int wpw, int bpl, int lds_tables_req, LaunchPlan *out)
+// Blocks of a launch resident on one compute unit, by LDS alone, capped at
+// the eight blocks of four waves a CU holds and at what the launch can use.
+long resident_blocks(const muca_job *j, size_t lds, long blocks)
+{
+    const long cus = j->n_cu > 0 ? j->n_cu : 256;
+    const long need = (blocks + cus - 1) / cus;
+    return std::min<long>(std::min<long>(need, 8), std::max<long>(1, (long)j->lds_cu / (long)lds));
+}
+
+// LDS layout of a sweep launch.  lds_tables_req and pack_req: 1 yes, 0 no,
+// -1 automatic.  Packed lattices need bpl == 1.
+bool plan_launch(const muca_job *j, int wpw, int bpl, int lds_tables_req, int pack_req, LaunchPlan *out)
 {
     const Layout &g = j->g;
     const int wpb = 4 / wpw;
-    auto build = [&](bool tables, bool hist, LaunchPlan *pl) {
+    auto build = [&](bool tables, bool hist, bool pack, LaunchPlan *pl) {
         size_t off = kLdsFixed;
         pl->off_hist = (int)off;
         if (hist) off += align_up(4 * ((size_t)g.V + 1), 16);
         pl->off_lat = (int)off;
-        off += align_up((size_t)wpb * g.Vp, 16);
+        off += align_up((size_t)wpb * (size_t)g.Vp / (pack ? 4 : 1), 16);
         pl->off_r = (int)off;
         if (tables) off += align_up(16 * ((size_t)g.V + 1 + 2 * kRPad), 16);
         pl->off_nb = (int)off;
@@ -229,14 +242,44 @@ bool plan_launch(const muca_job *j, int wpw, int bpl, int lds_tables_req, Launch
         pl->lds = off;
         pl->lds_tables = tables;
         pl->lds_hist = hist;
+        pl->pack = pack;
         return off <= (size_t)j->max_lds;
     };
+    // The per-block LDS histogram saves one HBM atomic per walker and sweep,
+    // but at large L it is as large as the lattices: it is kept only while it
+    // does not lower the number of blocks resident on a compute unit.  Packed
+    // lattices cost an extract per neighbour read; automatic packing takes
+    // them only when they raise the resident blocks.
+    const long blocks = ((long)g.n_walkers + wpb - 1) / wpb;
+    auto resident = [&](const LaunchPlan &pl) { return resident_blocks(j, pl.lds, blocks); };
     const bool try_tables[2] = {true, false};
     for (bool t : try_tables) {
         if (lds_tables_req == 1 && !t) continue;
         if (lds_tables_req == 0 && t) continue;
-        if (build(t, true, out)) return true;
-        if (build(t, false, out)) return true;
+        bool have = false;
+        LaunchPlan best{};
+        for (int pk = 0; pk < 2; ++pk) {
+            const bool pack = pk == 1;
+            if (pack && (bpl != 1 || pack_req == 0)) continue;
+            if (!pack && pack_req == 1) continue;
+            LaunchPlan with_hist, without, pl;
+            const bool fits_h = build(t, true, pack, &with_hist);
+            const bool fits_n = build(t, false, pack, &without);
+            if (fits_h && (!fits_n || resident(with_hist) >= resident(without)))
+                pl = with_hist;
+            else if (fits_n)
+                pl = without;
+            else
+                continue;
+            if (!have || resident(pl) > resident(best)) {
+                best = pl;
+                have = true;
+            }
+        }
+        if (have) {
+            *out = best;
+            return true;
+        }
     }
     return false;
 }
@@ -257,18 +300,19 @@ void default_launch(muca_job *j)
         wpw = 2;
     const int bpl = 1;
     LaunchPlan pl;
-    while (!plan_launch(j, wpw, bpl, -1, &pl) && wpw < 4) wpw *= 2;  // fewer walkers per block -> less LDS
+    while (!plan_launch(j, wpw, bpl, -1, -1, &pl) && wpw < 4) wpw *= 2;  // fewer walkers per block -> less LDS
     j->wpw = wpw;
     j->bpl = bpl;
     j->lds_tables_req = wpw == 1 ? 0 : -1;
-    if (wpw > 1 && plan_launch(j, wpw, bpl, 1, &pl) && pl.lds_tables) {
+    j->pack_req = -1;
+    if (wpw > 1 && plan_launch(j, wpw, bpl, 1, -1, &pl) && pl.lds_tables) {
         // staged tables only while every block still fits on the device at
         // once: a second wave of blocks costs more than the cached reads
         const long blocks = (nw + 4 / wpw - 1) / (4 / wpw);
         const long per_cu = std::max<long>(1, (long)j->max_lds / (long)pl.lds);
         if (blocks > per_cu * (long)(simds / 4)) j->lds_tables_req = 0;
     }
-    if (!plan_launch(j, wpw, bpl, j->lds_tables_req, &pl)) j->lds_tables_req = -1;
+    if (!plan_launch(j, wpw, bpl, j->lds_tables_req, -1, &pl)) j->lds_tables_req = -1;
 }
 
 int upload_tables(muca_job *j)
@@ -365,6 +409,10 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
     };
     if (hipGetDevice(&j->device) != hipSuccess) return bail(fail_device(hipGetLastError(), "hipGetDevice"));
     j->max_lds = query_max_lds(j->device);
+    if (hipDeviceGetAttribute(&j->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, j->device) !=
+            hipSuccess ||
+        j->lds_cu < j->max_lds)
+        j->lds_cu = j->max_lds;
     static_scratch_setup(j->device);
     if (hipDeviceGetAttribute(&j->n_cu, hipDeviceAttributeMultiprocessorCount, j->device) != hipSuccess)
         j->n_cu = 256;
@@ -385,8 +433,10 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
         std::vector<int> pos(V);
         for (int p = 0; p < V; ++p) pos[j->order[p]] = p;
         uint16_t *nb = reinterpret_cast<uint16_t *>(j->pin_tables + g.off_nb);
+        uint16_t *nb2 = reinterpret_cast<uint16_t *>(j->pin_tables + g.off_nb2);
         uint16_t *site = reinterpret_cast<uint16_t *>(j->pin_tables + g.off_site);
         std::memset(nb, 0, (size_t)12 * Vp);
+        std::memset(nb2, 0, (size_t)12 * Vp);
         std::memset(site, 0, (size_t)2 * Vp);
         for (int p = 0; p < V; ++p) {
             const int i = j->order[p];
@@ -394,7 +444,10 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
             const int nbr[6] = {(x + 1) % L + L * (y + L * z), (x + L - 1) % L + L * (y + L * z),
                                 x + L * ((y + 1) % L + L * z), x + L * ((y + L - 1) % L + L * z),
                                 x + L * (y + L * ((z + 1) % L)), x + L * (y + L * ((z + L - 1) % L))};
-            for (int dir = 0; dir < 6; ++dir) nb[(size_t)dir * Vp + p] = (uint16_t)pos[nbr[dir]];
+            for (int dir = 0; dir < 6; ++dir) {
+                nb[(size_t)dir * Vp + p] = (uint16_t)pos[nbr[dir]];
+                nb2[(size_t)dir * Vp + p] = (uint16_t)(2 * pos[nbr[dir]]);  // V <= 32768
+            }
             site[p] = (uint16_t)i;
         }
         unsigned char *dt = reinterpret_cast<unsigned char *>(j->d.tables);
@@ -433,7 +486,7 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     if (int rc = use_device(j)) return rc;
     const Layout &g = j->g;
     LaunchPlan pl;
-    if (!plan_launch(j, j->wpw, j->bpl, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
+    if (!plan_launch(j, j->wpw, j->bpl, j->lds_tables_req, j->pack_req, &pl)) return MUCA_E_SIZE;
     SweepArgs a;
     a.lattice = reinterpret_cast<int8_t *>(j->d.lattice);
     a.wstate = reinterpret_cast<int32_t *>(j->d.walker_state);
@@ -442,6 +495,7 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     a.bp = reinterpret_cast<const double *>(dt + g.off_bp);
     a.r = reinterpret_cast<const double *>(dt + g.off_r);
     a.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
+    a.nb2 = reinterpret_cast<const uint16_t *>(dt + g.off_nb2);
     a.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
     unsigned char *tail = reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256);
     a.err = reinterpret_cast<int *>(tail);
@@ -466,7 +520,7 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     while (left > 0) {
         const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
         a.n_sweeps = chunk;
-        HIP_TRY(launch_sweep(a, j->wpw, j->bpl, record, pl.lds_tables, pl.lds, j->stream));
+        HIP_TRY(launch_sweep(a, j->wpw, j->bpl, record, pl.lds_tables, pl.pack, pl.lds, j->stream));
         left -= chunk;
     }
     if (record) j->recorded += n_sweeps;
@@ -826,27 +880,31 @@ int muca_read_stats(muca_job *j, int64_t *out, int32_t reset)
     return MUCA_OK;
 }
 
-int muca_set_launch(muca_job *j, int32_t wpw, int32_t bpl, int32_t lds_tables)
+int muca_set_launch(muca_job *j, int32_t wpw, int32_t bpl, int32_t lds_tables, int32_t packing)
 {
     if (!j) return MUCA_E_INVAL;
-    if (!(wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2) || lds_tables < -1 || lds_tables > 1)
+    if (!(wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2) || lds_tables < -1 || lds_tables > 1 ||
+        packing < -1 || packing > 1 || (packing == 1 && bpl != 1))
         return MUCA_E_INVAL;
     LaunchPlan pl;
-    if (!plan_launch(j, wpw, bpl, lds_tables, &pl)) return MUCA_E_SIZE;
+    if (!plan_launch(j, wpw, bpl, lds_tables, packing, &pl)) return MUCA_E_SIZE;
     j->wpw = wpw;
     j->bpl = bpl;
     j->lds_tables_req = lds_tables;
+    j->pack_req = packing;
     return MUCA_OK;
 }
 
-int muca_get_launch(const muca_job *j, int32_t *wpw, int32_t *bpl, int32_t *lds_tables, int32_t *lds_bytes)
+int muca_get_launch(const muca_job *j, int32_t *wpw, int32_t *bpl, int32_t *lds_tables, int32_t *packing,
+                    int32_t *lds_bytes)
 {
     if (!j) return MUCA_E_INVAL;
     LaunchPlan pl;
-    if (!plan_launch(j, j->wpw, j->bpl, j->lds_tables_req, &pl)) return MUCA_E_SIZE;
+    if (!plan_launch(j, j->wpw, j->bpl, j->lds_tables_req, j->pack_req, &pl)) return MUCA_E_SIZE;
     if (wpw) *wpw = j->wpw;
     if (bpl) *bpl = j->bpl;
     if (lds_tables) *lds_tables = pl.lds_tables ? 1 : 0;
+    if (packing) *packing = pl.pack ? 1 : 0;
     if (lds_bytes) *lds_bytes = (int32_t)pl.lds;
     return MUCA_OK;
 }
@@ -904,6 +962,8 @@ struct muca_batch {
     std::vector<int> job_wpw;
     size_t total_walkers;
     size_t tab_bytes;  // LDS reserved for staged tables (0: every job reads them through the caches)
+    int pack_req;      // packed lattices: 1 yes, 0 no, -1 automatic
+    bool pack;         // the resolved choice
     hipEvent_t done;   // recorded after the last submitted launch
 };
 
@@ -921,6 +981,7 @@ struct BatchPlan {
     int wpw;             // 1, 2 or 4 for every job, or 0: job_wpw[k] for job k
     const int *job_wpw;  // n entries when wpw == 0
     size_t tab_bytes;    // LDS reserved for staged tables (0: none)
+    bool pack;           // lattices as 2-bit codes in LDS
     int wpw_of(int k) const { return wpw ? wpw : job_wpw[k]; }
 };
 
@@ -928,7 +989,8 @@ struct BatchPlan {
 size_t plan_lds(const BatchPlan &p)
 {
     size_t lat = 0;
-    for (int k = 0; k < p.n; ++k) lat = std::max(lat, (size_t)(4 / p.wpw_of(k)) * (size_t)p.jobs[k]->g.Vp);
+    for (int k = 0; k < p.n; ++k)
+        lat = std::max(lat, (size_t)(4 / p.wpw_of(k)) * (size_t)p.jobs[k]->g.Vp / (p.pack ? 4 : 1));
     return kLdsFixed + align_up(lat, 16);
 }
 
@@ -994,6 +1056,7 @@ int fill_batch(const BatchPlan &p, const int *order, BatchJob *bj, int2 *tiles)
         J.bp = reinterpret_cast<const double *>(dt + g.off_bp);
         J.r = reinterpret_cast<const double *>(dt + g.off_r);
         J.nb = reinterpret_cast<const uint16_t *>(dt + g.off_nb);
+        J.nb2 = reinterpret_cast<const uint16_t *>(dt + g.off_nb2);
         J.acc = reinterpret_cast<unsigned long long *>(j->d.accum);
         J.err = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(j->d.hist) + align_up(8 * ((size_t)g.V + 1), 256));
         J.V = g.V;
@@ -1035,7 +1098,7 @@ int enqueue_batch(const BatchPlan &p, int bpl, int blocks, const BatchJob *d_job
         const int chunk = (int)std::min<int64_t>(left, kMaxSweepsPerLaunch);
         a.n_sweeps = chunk;
         HIP_TRY(launch_zero(d_counter, 16, stream));
-        HIP_TRY(launch_batch(a, p.wpw, bpl, record, lds, blocks, stream));
+        HIP_TRY(launch_batch(a, p.wpw, bpl, record, p.pack, lds, blocks, stream));
         left -= chunk;
     }
     if (record)
@@ -1051,7 +1114,38 @@ BatchPlan plan_of(const muca_batch *b, int wpw)
     p.wpw = wpw;
     p.job_wpw = b->job_wpw.data();
     p.tab_bytes = b->tab_bytes;
+    p.pack = b->pack;
     return p;
+}
+
+// Packing and staged tables of a batched launch.  pack_req 1 or 0 forces the
+// packing (packed needs bpl == 1); -1 takes packed lattices only when they
+// raise the blocks resident on a compute unit (the staged-table budget then
+// also grows).  Returns false if no choice fits in a block's LDS.
+bool resolve_batch_plan(BatchPlan &p, int bpl, int pack_req)
+{
+    const muca_job *j0 = p.jobs[0];
+    bool have = false;
+    BatchPlan best = p;
+    long best_res = 0;
+    for (int pk = 0; pk < 2; ++pk) {
+        const bool pack = pk == 1;
+        if (pack && (bpl != 1 || pack_req == 0)) continue;
+        if (!pack && pack_req == 1) continue;
+        BatchPlan q = p;
+        q.pack = pack;
+        q.tab_bytes = 0;
+        if (plan_lds(q) > (size_t)j0->max_lds) continue;
+        q.tab_bytes = plan_tab_bytes(q);
+        const long res = std::min<long>(8, std::max<long>(1, (long)j0->lds_cu / (long)(plan_lds(q) + q.tab_bytes)));
+        if (!have || res > best_res) {
+            best = q;
+            best_res = res;
+            have = true;
+        }
+    }
+    if (have) p = best;
+    return have;
 }
 
 // Waves per walker of each job in a launch that mixes them (an opt-in shape:
@@ -1222,18 +1316,22 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
     b->bpl = 1;
     b->blocks = 0;
     b->tab_bytes = 0;
+    b->pack_req = -1;
+    b->pack = false;
     choose_job_wpw(b);  // the shape of a per-job launch, if a caller asks for one
-    const int max_lds = jobs[0]->max_lds;
-    while (plan_lds(plan_of(b, b->wpw)) > (size_t)max_lds && b->wpw < 4) b->wpw *= 2;
-    if (plan_lds(plan_of(b, b->wpw)) > (size_t)max_lds) {
+    BatchPlan p = plan_of(b, b->wpw);
+    while (!resolve_batch_plan(p, b->bpl, b->pack_req) && p.wpw < 4) p.wpw *= 2;
+    if (!resolve_batch_plan(p, b->bpl, b->pack_req)) {
         delete b;
         return MUCA_E_SIZE;
     }
+    b->wpw = p.wpw;
+    b->pack = p.pack;
+    b->tab_bytes = p.tab_bytes;
     if (int rc = use_device(jobs[0])) {
         delete b;
         return rc;
     }
-    b->tab_bytes = plan_tab_bytes(plan_of(b, b->wpw));
     b->done = nullptr;
     if (int rc = upload_batch(b)) {
         delete b;
@@ -1247,31 +1345,36 @@ int muca_batch_create(muca_job *const *jobs, int32_t n_jobs, void *dev_buffer, s
     return MUCA_OK;
 }
 
-int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t blocks)
+int muca_batch_set_launch(muca_batch *b, int32_t wpw, int32_t bpl, int32_t blocks, int32_t packing)
 {
-    if (!b || !(wpw == 0 || wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2)) return MUCA_E_INVAL;
-    if (plan_lds(plan_of(b, wpw)) > (size_t)b->jobs[0]->max_lds) return MUCA_E_SIZE;
+    if (!b || !(wpw == 0 || wpw == 1 || wpw == 2 || wpw == 4) || !(bpl == 1 || bpl == 2) || packing < -1 ||
+        packing > 1 || (packing == 1 && bpl != 1))
+        return MUCA_E_INVAL;
+    BatchPlan p = plan_of(b, wpw);
+    if (!resolve_batch_plan(p, bpl, packing)) return MUCA_E_SIZE;
     if (int rc = use_device(b->jobs[0])) return rc;
     const int old = b->wpw;
+    const bool old_pack = b->pack;
+    const size_t old_tab = b->tab_bytes;
     b->wpw = wpw;
     b->bpl = bpl;
     b->blocks = blocks > 0 ? blocks : 0;
-    if (old != wpw) {
-        b->tab_bytes = 0;
-        b->tab_bytes = plan_tab_bytes(plan_of(b, wpw));
-        return upload_batch(b);
-    }
+    b->pack_req = packing;
+    b->pack = p.pack;
+    b->tab_bytes = p.tab_bytes;
+    if (old != wpw || old_pack != b->pack || old_tab != b->tab_bytes) return upload_batch(b);
     return MUCA_OK;
 }
 
 int muca_batch_get_launch(const muca_batch *b, int32_t *waves_per_walker, int32_t *blocks_per_lane,
-                          int32_t *lds_bytes)
+                          int32_t *packing, int32_t *lds_bytes)
 {
     if (!b) return MUCA_E_INVAL;
     const BatchPlan p = plan_of(b, b->wpw);
     if (waves_per_walker)
         for (int k = 0; k < p.n; ++k) waves_per_walker[k] = p.wpw_of(k);
     if (blocks_per_lane) *blocks_per_lane = b->bpl;
+    if (packing) *packing = b->pack ? 1 : 0;
     if (lds_bytes) *lds_bytes = (int32_t)(plan_lds(p) + p.tab_bytes);
     return MUCA_OK;
 }
@@ -1344,11 +1447,10 @@ int muca_batch_sweep_static(muca_job *const *jobs, int32_t n_jobs, int64_t n_swe
     p.wpw = 1;
     p.job_wpw = nullptr;
     p.tab_bytes = 0;
-    const int max_lds = jobs[0]->max_lds;
-    while (plan_lds(p) > (size_t)max_lds && p.wpw < 4) p.wpw *= 2;
-    if (plan_lds(p) > (size_t)max_lds) return MUCA_E_SIZE;
+    p.pack = false;
+    while (!resolve_batch_plan(p, 1, -1) && p.wpw < 4) p.wpw *= 2;
+    if (!resolve_batch_plan(p, 1, -1)) return MUCA_E_SIZE;
     if (count_tiles(p) > kStaticMaxTiles) return MUCA_E_SIZE;
-    p.tab_bytes = plan_tab_bytes(p);
     if (n_sweeps == 0) return MUCA_OK;
     const int device = jobs[0]->device;
     if (int rc = use_device(jobs[0])) return rc;

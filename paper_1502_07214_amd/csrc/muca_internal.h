@@ -24,7 +24,7 @@ struct Layout {
     int cls[kMaxClasses + 1];  // colour class c covers positions [cls[c], cls[c+1])
     int n_walkers, max_delta;
     size_t lattice_bytes, state_bytes, hist_bytes, tables_bytes, accum_bytes, obs_bytes;
-    size_t off_bp, off_r, off_lnw, off_nb, off_site;  // byte offsets inside tables
+    size_t off_bp, off_r, off_lnw, off_nb, off_nb2, off_site;  // byte offsets inside tables
     size_t off_obs_lnp, off_obs_sums;                 // byte offsets inside obs
 };
 
@@ -36,6 +36,7 @@ struct SweepArgs {
     const double *bp;              // 25 (+pad) thresholds 2^31 exp(-beta k)
     const double *r;               // (V+1+2*kRPad) x 2: [E+kRPad][0] = R_-, [E+kRPad][1] = R_+
     const uint16_t *nb;            // 6 x Vp neighbour positions
+    const uint16_t *nb2;           // the same, doubled (packed lattices: bit offset of a 2-bit code)
     unsigned long long *acc;       // 7 x (V+1) production sums
     int *err;                      // device error word (the tail of the hist buffer)
     unsigned long long *stats;     // null, or [passes, rounds, accepted moves]
@@ -85,6 +86,7 @@ struct BatchJob {
     const double *bp;
     const double *r;
     const uint16_t *nb;
+    const uint16_t *nb2;
     unsigned long long *acc;
     int *err;
     int V, Vp, n_walkers, n_classes;
@@ -107,12 +109,14 @@ struct BatchArgs {
 
 // Launchers (muca_kernels.hip).  Return the hipError_t of the launch.
 hipError_t launch_init(const InitArgs &a, hipStream_t s);
+// pack: lattices as 2-bit codes in LDS (blocks_per_lane 1 only)
 hipError_t launch_sweep(const SweepArgs &a, int waves_per_walker, int blocks_per_lane, bool record,
-                        bool lds_tables, size_t lds_bytes, hipStream_t s);
+                        bool lds_tables, bool pack, size_t lds_bytes, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s);
 hipError_t launch_log_hist(const LogHistArgs &a, hipStream_t s);
 // blocks <= 0: as many blocks as fit on the device at once
-hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, size_t lds, int blocks, hipStream_t s);
+hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, bool pack, size_t lds, int blocks,
+                        hipStream_t s);
 
 }  // namespace muca

@@ -16,10 +16,15 @@
 //    ends after at most (sites in the pass + 1) rounds.  When several waves
 //    share a walker, each wave iterates its own chunk without barriers and
 //    the waves exchange only chunk totals between such inner iterations.
-//  * Lattices live in LDS as one int8 per site in colour-major position order;
-//    a lane owns 4 consecutive positions (one Philox block) per group, so spin
-//    writes are whole dwords with no atomics.  Thresholds B', R_+-, and the
-//    neighbour table sit in LDS when they fit, else are read through L1/L2.
+//  * Lattices live in LDS in colour-major position order, as one int8 per site
+//    or (PACK) as 2-bit two's-complement codes, four sites per byte, a quarter
+//    of the LDS (more resident walkers when lattices bound occupancy, at one
+//    extra field extract per neighbour read).  A lane owns 4 consecutive
+//    positions (one Philox block) per group, so spin writes are whole dwords
+//    (int8) or bytes (packed) with no atomics.  In HBM lattices are always
+//    int8; a packed launch packs them on the way in and unpacks them on the
+//    way out.  Thresholds B', R_+-, and the neighbour table sit in LDS when
+//    they fit, else are read through L1/L2.
 //  * Histograms: one LDS atomic per walker per sweep, flushed to HBM with one
 //    64-bit atomic per nonzero bin at the end of the launch (when the histogram
 //    fits in LDS next to the lattices; otherwise, and in batched launches, one
@@ -65,6 +70,39 @@ __device__ __forceinline__ int clamp0(int x, int hi)
     return r;
 }
 
+// 2-bit codes of a packed lattice: site p is the sign-extended field at bit
+// 2p mod 32 of dword p / 16 (-1 = 0b11, 0 = 0b00, +1 = 0b01).  The packed
+// neighbour table holds 2p, whose low five bits are that field's offset.
+__device__ __forceinline__ int code_field(unsigned word, unsigned off2)
+{
+    return __builtin_amdgcn_sbfe((int)word, off2, 2u);
+}
+
+// 16 int8 spins -> one dword of 2-bit codes, and back.
+__device__ __forceinline__ unsigned pack16(uint4 v)
+{
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    unsigned out = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) out |= ((w[i] >> (8 * t)) & 3u) << (2 * (4 * i + t));
+    return out;
+}
+
+__device__ __forceinline__ uint4 unpack16(unsigned x)
+{
+    unsigned w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        unsigned d = 0u;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) d |= ((unsigned)code_field(x, 2u * (4 * i + t)) & 0xffu) << (8 * t);
+        w[i] = d;
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // Proposal: the b-th (ascending) of the two spin values other than s.
 __device__ __forceinline__ int propose(int s, int b)
 {
@@ -75,12 +113,13 @@ __device__ __forceinline__ int propose(int s, int b)
 // One pass: the sites of one colour class whose Philox blocks start at jbase,
 // BPL consecutive blocks (4*BPL positions) per lane, GL lanes per walker.
 // ---------------------------------------------------------------------------
-template <int WPW, int BPL>
+template <int WPW, int BPL, bool PACK>
 struct Walker {
     static constexpr int GL = 64 * WPW;  // lanes per walker
     static constexpr int NS = 4 * BPL;   // sites per lane per pass
     static constexpr int WPB = 4 / WPW;  // walkers per block
-    int8_t *lat;                         // this walker's lattice in LDS
+    static_assert(!PACK || BPL == 1, "packed lattices are read one Philox block per lane");
+    int8_t *lat;                         // this walker's lattice in LDS (PACK: 2-bit codes)
     const double *R;                     // [E][0] = R_-, [E][1] = R_+
     const double *sBp;                   // B'[25] in LDS
     int *sX;                             // [2][4] per-wave exchange words
@@ -109,13 +148,27 @@ struct Walker {
         for (int q = 0; q < BPL; ++q) {
             const int jb = jb0 + q;
             const int jbc = jb < j1 ? jb : j0;
-            words[q] = *reinterpret_cast<const int *>(lat + 4 * jbc);
+            if constexpr (PACK) {
+                // the four sites of block jbc are byte jbc; neighbours hold 2p
+                const unsigned *lat32 = reinterpret_cast<const unsigned *>(lat);
+                words[q] = (int)reinterpret_cast<const uint8_t *>(lat)[jbc];
 #pragma unroll
-            for (int dir = 0; dir < 6; ++dir) {
-                nbs[q][dir][0] = lat[nq[q][dir].x & 0xffffu];
-                nbs[q][dir][1] = lat[nq[q][dir].x >> 16];
-                nbs[q][dir][2] = lat[nq[q][dir].y & 0xffffu];
-                nbs[q][dir][3] = lat[nq[q][dir].y >> 16];
+                for (int dir = 0; dir < 6; ++dir) {
+                    const unsigned x = nq[q][dir].x, y = nq[q][dir].y;
+                    nbs[q][dir][0] = code_field(lat32[(x >> 5) & 0x7ffu], x);
+                    nbs[q][dir][1] = code_field(lat32[x >> 21], x >> 16);
+                    nbs[q][dir][2] = code_field(lat32[(y >> 5) & 0x7ffu], y);
+                    nbs[q][dir][3] = code_field(lat32[y >> 21], y >> 16);
+                }
+            } else {
+                words[q] = *reinterpret_cast<const int *>(lat + 4 * jbc);
+#pragma unroll
+                for (int dir = 0; dir < 6; ++dir) {
+                    nbs[q][dir][0] = lat[nq[q][dir].x & 0xffffu];
+                    nbs[q][dir][1] = lat[nq[q][dir].x >> 16];
+                    nbs[q][dir][2] = lat[nq[q][dir].y & 0xffffu];
+                    nbs[q][dir][3] = lat[nq[q][dir].y >> 16];
+                }
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -141,7 +194,7 @@ struct Walker {
                 const int k = 4 * q + t;
                 const int p = 4 * jbc + t;
                 valid[k] = blk && p >= P0 && p < P1;
-                const int s = (int)(int8_t)(word >> (8 * t));
+                const int s = PACK ? code_field((unsigned)word, 2u * t) : (int)(int8_t)(word >> (8 * t));
                 const uint32_t xw = x.v[t];
                 const int sn = propose(s, (int)(xw & 1u));
                 u[k] = (double)(xw >> 1);
@@ -220,9 +273,17 @@ struct Walker {
                 for (int t = 0; t < 4; ++t) {
                     const int k = 4 * q + t;
                     const bool a = ddv[k] != 0 ? c[k] : ((acc0 >> k) & 1u) != 0u;
-                    nw |= ((unsigned)(a ? snew[k] : sold[k]) & 0xffu) << (8 * t);
+                    if (PACK)
+                        nw |= ((unsigned)(a ? snew[k] : sold[k]) & 3u) << (2 * t);
+                    else
+                        nw |= ((unsigned)(a ? snew[k] : sold[k]) & 0xffu) << (8 * t);
                 }
-                if (jb < j1) *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
+                if (jb < j1) {
+                    if (PACK)
+                        reinterpret_cast<uint8_t *>(lat)[jb] = (uint8_t)nw;
+                    else
+                        *reinterpret_cast<unsigned *>(lat + 4 * jb) = nw;
+                }
             }
         };
         auto exchange = [&](int (&no)[4]) {
@@ -336,10 +397,11 @@ struct Walker {
 //   exactly the NCP passes listed in the arguments and each lane keeps the
 //   neighbour positions of its sites in registers for the whole launch.
 // ---------------------------------------------------------------------------
-template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP, bool PACK>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, unsigned char *smem)
 {
-    using W = Walker<WPW, BPL>;
+    using W = Walker<WPW, BPL, PACK>;
+    constexpr int LAT_DIV = PACK ? 4 : 1;  // LDS bytes per site: 1 / LAT_DIV
 
     double *sBp = reinterpret_cast<double *>(smem);
     int *sX = reinterpret_cast<int *>(smem + 256);                   // [8] exchange words
@@ -364,7 +426,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     if (a.lds_hist)
         for (int e = tid; e <= V; e += kBlock) sHist[e] = 0u;
     const double *R = a.r + 2 * kRPad;  // R[2E + 1] = R_+(E), R[2E] = R_-(E), E in [-kRPad, V + kRPad]
-    const uint16_t *NB = a.nb;
+    const uint16_t *NB = PACK ? a.nb2 : a.nb;  // positions, or twice the positions for packed lattices
     if (LDS_TABLES) {
         double *sR = reinterpret_cast<double *>(smem + a.lds_off_r);
         const int nr = 2 * (V + 1 + 2 * kRPad);
@@ -372,18 +434,23 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
         R = sR + 2 * kRPad;
         if (NCP == 0) {
             uint16_t *sNB = reinterpret_cast<uint16_t *>(smem + a.lds_off_nb);
-            const uint4 *gnb = reinterpret_cast<const uint4 *>(a.nb);
+            const uint4 *gnb = reinterpret_cast<const uint4 *>(NB);
             uint4 *lnb = reinterpret_cast<uint4 *>(sNB);
             const int nq = (6 * Vp * 2) / 16;
             for (int k = tid; k < nq; k += kBlock) lnb[k] = gnb[k];
             NB = sNB;
         }
     }
-    int8_t *lat = sLat + (size_t)slot * Vp;
+    int8_t *lat = sLat + (size_t)slot * (Vp / LAT_DIV);
     {
-        uint4 *dst = reinterpret_cast<uint4 *>(lat);
         const uint4 *src = reinterpret_cast<const uint4 *>(a.lattice + (size_t)(live ? walker : 0) * Vp);
-        for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = live ? src[k] : make_uint4(0, 0, 0, 0);
+        if (PACK) {
+            unsigned *dst = reinterpret_cast<unsigned *>(lat);
+            for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = live ? pack16(src[k]) : 0u;
+        } else {
+            uint4 *dst = reinterpret_cast<uint4 *>(lat);
+            for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = live ? src[k] : make_uint4(0, 0, 0, 0);
+        }
     }
     int EJ0 = 0, M0 = 0;
     uint32_t sweep = 0;
@@ -420,7 +487,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
                 const int jbc = jb < j1 ? jb : (a.pass_p0[cp] >> 2);
 #pragma unroll
                 for (int dir = 0; dir < 6; ++dir)
-                    nbc[cp][q][dir] = *reinterpret_cast<const uint2 *>(a.nb + dir * Vp + 4 * jbc);
+                    nbc[cp][q][dir] = *reinterpret_cast<const uint2 *>(NB + dir * Vp + 4 * jbc);
             }
         }
     }
@@ -529,8 +596,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     }
     if (live) {
         uint4 *dst = reinterpret_cast<uint4 *>(a.lattice + (size_t)walker * Vp);
-        const uint4 *src = reinterpret_cast<const uint4 *>(lat);
-        for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = src[k];
+        if (PACK) {
+            const unsigned *src = reinterpret_cast<const unsigned *>(lat);
+            for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = unpack16(src[k]);
+        } else {
+            const uint4 *src = reinterpret_cast<const uint4 *>(lat);
+            for (int k = lg; k < Vp / 16; k += W::GL) dst[k] = src[k];
+        }
         if (lg == 0)
             reinterpret_cast<int4 *>(a.wstate)[walker] =
                 make_int4((int)((unsigned)EJ0 + ej), wk.ED, (int)((unsigned)M0 + m), (int)sweep);
@@ -542,11 +614,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
         }
 }
 
-template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP, bool PACK>
 __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    sweep_tile<WPW, BPL, RECORD, LDS_TABLES, NCP>(a, (int)blockIdx.x * (4 / WPW), smem);
+    sweep_tile<WPW, BPL, RECORD, LDS_TABLES, NCP, PACK>(a, (int)blockIdx.x * (4 / WPW), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,22 +632,22 @@ __global__ __launch_bounds__(kBlock) void muca_sweep_kernel(SweepArgs a)
 // waves per walker from each tile's job (1 or 4), so the walkers of large
 // lattices get a whole block while small ones share one.
 // ---------------------------------------------------------------------------
-template <int WPW, int BPL, bool RECORD>
+template <int WPW, int BPL, bool RECORD, bool PACK>
 __device__ __forceinline__ void batch_tile(const BatchArgs &b, const BatchJob &J, SweepArgs &a, int walker0,
                                            unsigned char *smem)
 {
     if (J.lds_tables) {
         a.lds_off_r = b.lds_off_tab;
         a.lds_off_nb = b.lds_off_tab + ((16 * (J.V + 1 + 2 * kRPad) + 15) & ~15);
-        sweep_tile<WPW, BPL, RECORD, true, 0>(a, walker0, smem);
+        sweep_tile<WPW, BPL, RECORD, true, 0, PACK>(a, walker0, smem);
     } else {
         a.lds_off_r = 0;
         a.lds_off_nb = 0;
-        sweep_tile<WPW, BPL, RECORD, false, 0>(a, walker0, smem);
+        sweep_tile<WPW, BPL, RECORD, false, 0, PACK>(a, walker0, smem);
     }
 }
 
-template <int WPW, int BPL, bool RECORD>
+template <int WPW, int BPL, bool RECORD, bool PACK>
 __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -595,6 +667,7 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
         a.bp = J.bp;
         a.r = J.r;
         a.nb = J.nb;
+        a.nb2 = J.nb2;
         a.acc = J.acc;
         a.err = J.err;
         a.stats = nullptr;
@@ -616,11 +689,11 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
         a.lds_off_lat = b.lds_off_lat;
         if constexpr (WPW == 0) {
             if (J.wpw == 4)
-                batch_tile<4, BPL, RECORD>(b, J, a, tile.y, smem);
+                batch_tile<4, BPL, RECORD, PACK>(b, J, a, tile.y, smem);
             else
-                batch_tile<1, BPL, RECORD>(b, J, a, tile.y, smem);
+                batch_tile<1, BPL, RECORD, PACK>(b, J, a, tile.y, smem);
         } else {
-            batch_tile<WPW, BPL, RECORD>(b, J, a, tile.y, smem);
+            batch_tile<WPW, BPL, RECORD, PACK>(b, J, a, tile.y, smem);
         }
     }
 }
@@ -873,10 +946,10 @@ hipError_t launch_reweight(const ReweightArgs &a, int n_delta, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP>
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, int NCP, bool PACK>
 static hipError_t launch_sweep_t(const SweepArgs &a, size_t lds, hipStream_t s)
 {
-    auto kern = muca_sweep_kernel<WPW, BPL, RECORD, LDS_TABLES, NCP>;
+    auto kern = muca_sweep_kernel<WPW, BPL, RECORD, LDS_TABLES, NCP, PACK>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -886,34 +959,34 @@ static hipError_t launch_sweep_t(const SweepArgs &a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int WPW, int BPL, bool RECORD, bool LDS_TABLES>
+template <int WPW, int BPL, bool RECORD, bool LDS_TABLES, bool PACK>
 static hipError_t launch_sweep_n(const SweepArgs &a, size_t lds, hipStream_t s)
 {
     if constexpr (BPL == 1) {
         switch (a.n_pass) {
-        case 2: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 2>(a, lds, s);
-        case 3: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 3>(a, lds, s);
-        case 4: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 4>(a, lds, s);
+        case 2: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 2, PACK>(a, lds, s);
+        case 3: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 3, PACK>(a, lds, s);
+        case 4: return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 4, PACK>(a, lds, s);
         default: break;
         }
     }
-    return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 0>(a, lds, s);
+    return launch_sweep_t<WPW, BPL, RECORD, LDS_TABLES, 0, PACK>(a, lds, s);
 }
 
-template <int WPW, int BPL>
+template <int WPW, int BPL, bool PACK>
 static hipError_t launch_sweep_b(const SweepArgs &a, bool record, bool lds_tables, size_t lds, hipStream_t s)
 {
     if (record)
-        return lds_tables ? launch_sweep_n<WPW, BPL, true, true>(a, lds, s)
-                          : launch_sweep_n<WPW, BPL, true, false>(a, lds, s);
-    return lds_tables ? launch_sweep_n<WPW, BPL, false, true>(a, lds, s)
-                      : launch_sweep_n<WPW, BPL, false, false>(a, lds, s);
+        return lds_tables ? launch_sweep_n<WPW, BPL, true, true, PACK>(a, lds, s)
+                          : launch_sweep_n<WPW, BPL, true, false, PACK>(a, lds, s);
+    return lds_tables ? launch_sweep_n<WPW, BPL, false, true, PACK>(a, lds, s)
+                      : launch_sweep_n<WPW, BPL, false, false, PACK>(a, lds, s);
 }
 
-template <int WPW, int BPL, bool RECORD>
+template <int WPW, int BPL, bool RECORD, bool PACK>
 static hipError_t launch_batch_t(const BatchArgs &b, size_t lds, int blocks, hipStream_t s)
 {
-    auto kern = muca_batch_kernel<WPW, BPL, RECORD>;
+    auto kern = muca_batch_kernel<WPW, BPL, RECORD, PACK>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -930,33 +1003,51 @@ static hipError_t launch_batch_t(const BatchArgs &b, size_t lds, int blocks, hip
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, size_t lds, int blocks, hipStream_t s)
+template <int WPW>
+static hipError_t launch_batch_w(const BatchArgs &b, int bpl, bool record, bool pack, size_t lds, int blocks,
+                                 hipStream_t s)
 {
-    if (wpw == 0) {
-        if (bpl == 1) return record ? launch_batch_t<0, 1, true>(b, lds, blocks, s) : launch_batch_t<0, 1, false>(b, lds, blocks, s);
-        return record ? launch_batch_t<0, 2, true>(b, lds, blocks, s) : launch_batch_t<0, 2, false>(b, lds, blocks, s);
+    if (bpl == 1) {
+        if (pack)
+            return record ? launch_batch_t<WPW, 1, true, true>(b, lds, blocks, s)
+                          : launch_batch_t<WPW, 1, false, true>(b, lds, blocks, s);
+        return record ? launch_batch_t<WPW, 1, true, false>(b, lds, blocks, s)
+                      : launch_batch_t<WPW, 1, false, false>(b, lds, blocks, s);
     }
-    if (wpw == 1) {
-        if (bpl == 1) return record ? launch_batch_t<1, 1, true>(b, lds, blocks, s) : launch_batch_t<1, 1, false>(b, lds, blocks, s);
-        return record ? launch_batch_t<1, 2, true>(b, lds, blocks, s) : launch_batch_t<1, 2, false>(b, lds, blocks, s);
-    }
-    if (wpw == 2) {
-        if (bpl == 1) return record ? launch_batch_t<2, 1, true>(b, lds, blocks, s) : launch_batch_t<2, 1, false>(b, lds, blocks, s);
-        return record ? launch_batch_t<2, 2, true>(b, lds, blocks, s) : launch_batch_t<2, 2, false>(b, lds, blocks, s);
-    }
-    if (bpl == 1) return record ? launch_batch_t<4, 1, true>(b, lds, blocks, s) : launch_batch_t<4, 1, false>(b, lds, blocks, s);
-    return record ? launch_batch_t<4, 2, true>(b, lds, blocks, s) : launch_batch_t<4, 2, false>(b, lds, blocks, s);
+    return record ? launch_batch_t<WPW, 2, true, false>(b, lds, blocks, s)
+                  : launch_batch_t<WPW, 2, false, false>(b, lds, blocks, s);
 }
 
-hipError_t launch_sweep(const SweepArgs &a, int wpw, int bpl, bool record, bool lds_tables, size_t lds,
+// pack: packed lattices (only with bpl == 1; the host never asks otherwise)
+hipError_t launch_batch(const BatchArgs &b, int wpw, int bpl, bool record, bool pack, size_t lds, int blocks,
                         hipStream_t s)
 {
-    if (wpw == 1) return bpl == 1 ? launch_sweep_b<1, 1>(a, record, lds_tables, lds, s)
-                                  : launch_sweep_b<1, 2>(a, record, lds_tables, lds, s);
-    if (wpw == 2) return bpl == 1 ? launch_sweep_b<2, 1>(a, record, lds_tables, lds, s)
-                                  : launch_sweep_b<2, 2>(a, record, lds_tables, lds, s);
-    return bpl == 1 ? launch_sweep_b<4, 1>(a, record, lds_tables, lds, s)
-                    : launch_sweep_b<4, 2>(a, record, lds_tables, lds, s);
+    if (pack && bpl != 1) return hipErrorInvalidValue;
+    switch (wpw) {
+    case 0: return launch_batch_w<0>(b, bpl, record, pack, lds, blocks, s);
+    case 1: return launch_batch_w<1>(b, bpl, record, pack, lds, blocks, s);
+    case 2: return launch_batch_w<2>(b, bpl, record, pack, lds, blocks, s);
+    default: return launch_batch_w<4>(b, bpl, record, pack, lds, blocks, s);
+    }
+}
+
+template <int WPW>
+static hipError_t launch_sweep_w(const SweepArgs &a, int bpl, bool record, bool lds_tables, bool pack, size_t lds,
+                                 hipStream_t s)
+{
+    if (bpl == 1)
+        return pack ? launch_sweep_b<WPW, 1, true>(a, record, lds_tables, lds, s)
+                    : launch_sweep_b<WPW, 1, false>(a, record, lds_tables, lds, s);
+    return launch_sweep_b<WPW, 2, false>(a, record, lds_tables, lds, s);
+}
+
+hipError_t launch_sweep(const SweepArgs &a, int wpw, int bpl, bool record, bool lds_tables, bool pack, size_t lds,
+                        hipStream_t s)
+{
+    if (pack && bpl != 1) return hipErrorInvalidValue;
+    if (wpw == 1) return launch_sweep_w<1>(a, bpl, record, lds_tables, pack, lds, s);
+    if (wpw == 2) return launch_sweep_w<2>(a, bpl, record, lds_tables, pack, lds, s);
+    return launch_sweep_w<4>(a, bpl, record, lds_tables, pack, lds, s);
 }
 
 }  // namespace muca

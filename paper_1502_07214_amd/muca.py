@@ -85,8 +85,8 @@ def lib():
     L.muca_reset_accum.argtypes = [vp]
     L.muca_set_stats.argtypes = [vp, i32]
     L.muca_read_stats.argtypes = [vp, P(i64), i32]
-    L.muca_set_launch.argtypes = [vp, i32, i32, i32]
-    L.muca_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    L.muca_set_launch.argtypes = [vp, i32, i32, i32, i32]
+    L.muca_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
     L.muca_host_tables.argtypes = [i32, dbl, P(dbl), i32, i32, P(dbl), P(dbl), P(dbl)]
     L.muca_host_walls.argtypes = [i32, dbl, i32, i32, P(dbl)]
     L.muca_set_window.argtypes = [vp, i32, i32]
@@ -99,8 +99,8 @@ def lib():
     L.muca_free.restype = None
     L.muca_batch_query_size.argtypes = [P(vp), i32, sz]
     L.muca_batch_create.argtypes = [P(vp), i32, vp, ctypes.c_size_t, P(vp)]
-    L.muca_batch_set_launch.argtypes = [vp, i32, i32, i32]
-    L.muca_batch_get_launch.argtypes = [vp, P(i32), P(i32), P(i32)]
+    L.muca_batch_set_launch.argtypes = [vp, i32, i32, i32, i32]
+    L.muca_batch_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     L.muca_batch_sweep.argtypes = [vp, i64, u32]
     L.muca_batch_sweep_static.argtypes = [P(vp), i32, i64, u32]
     L.muca_batch_submit.argtypes = [vp, i64, u32]
@@ -344,13 +344,15 @@ class MucaJob:
         _check(lib().muca_read_stats(self._h, _p(v, ctypes.c_int64), 1 if reset else 0), "muca_read_stats")
         return {"passes": int(v[0]), "rounds": int(v[1]), "accepted": int(v[2])}
 
-    def set_launch(self, waves_per_walker: int, blocks_per_lane: int, lds_tables: int = -1):
-        _check(lib().muca_set_launch(self._h, waves_per_walker, blocks_per_lane, lds_tables), "muca_set_launch")
+    def set_launch(self, waves_per_walker: int, blocks_per_lane: int, lds_tables: int = -1, packing: int = -1):
+        _check(lib().muca_set_launch(self._h, waves_per_walker, blocks_per_lane, lds_tables, packing),
+               "muca_set_launch")
 
     def get_launch(self) -> dict:
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(5)]
         _check(lib().muca_get_launch(self._h, *[ctypes.byref(x) for x in v]), "muca_get_launch")
-        return dict(zip(("waves_per_walker", "blocks_per_lane", "lds_tables", "lds_bytes"), [x.value for x in v]))
+        return dict(zip(("waves_per_walker", "blocks_per_lane", "lds_tables", "packed", "lds_bytes"),
+                        [x.value for x in v]))
 
     def free(self):
         if getattr(self, "_h", None):
@@ -384,15 +386,18 @@ class MucaBatch:
                    "muca_batch_create")
         self._h = h
 
-    def set_launch(self, waves_per_walker: int, blocks_per_lane: int, blocks: int = 0):
-        _check(lib().muca_batch_set_launch(self._h, waves_per_walker, blocks_per_lane, blocks), "muca_batch_set_launch")
+    def set_launch(self, waves_per_walker: int, blocks_per_lane: int, blocks: int = 0, packing: int = -1):
+        _check(lib().muca_batch_set_launch(self._h, waves_per_walker, blocks_per_lane, blocks, packing),
+               "muca_batch_set_launch")
 
     def get_launch(self) -> dict:
-        """The shape in use: waves per walker of each job (in the order given), blocks per lane, LDS bytes."""
+        """The shape in use: waves per walker of each job (in the order given),
+        blocks per lane, packing, LDS bytes."""
         w = (ctypes.c_int32 * len(self.jobs))()
-        b, lds = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().muca_batch_get_launch(self._h, w, ctypes.byref(b), ctypes.byref(lds)), "muca_batch_get_launch")
-        return {"waves_per_walker": list(w), "blocks_per_lane": b.value, "lds_bytes": lds.value}
+        b, pk, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().muca_batch_get_launch(self._h, w, ctypes.byref(b), ctypes.byref(pk), ctypes.byref(lds)),
+               "muca_batch_get_launch")
+        return {"waves_per_walker": list(w), "blocks_per_lane": b.value, "packed": pk.value, "lds_bytes": lds.value}
 
     def sweep(self, n_sweeps: int, record: bool = False):
         _check(lib().muca_batch_sweep(self._h, int(n_sweeps), MUCA_RECORD if record else 0), "muca_batch_sweep")

@@ -4,6 +4,8 @@
     python -m paper_1502_07214_amd.profile_runs sweep   # the benchmark's sweep launches (L=12, 256 walkers)
     python -m paper_1502_07214_amd.profile_runs saturation  # L=8, 65 536 walkers, 10 + 100 sweeps
     python -m paper_1502_07214_amd.profile_runs batched     # 19 mixed jobs: 10 batched launches of 1000 sweeps
+    python -m paper_1502_07214_amd.profile_runs c3          # L=16, T=1, 1024 walkers: 3 iterations of 2*10^4 sweeps
+    python -m paper_1502_07214_amd.profile_runs bigL L W P  # L^3, W walkers, packing P (0, 1, -1 auto): 3 x 200 sweeps
 
 `copy` calibrates the FETCH_SIZE / WRITE_SIZE counters: each copy moves exactly
 2^30 bytes in and 2^30 bytes out of HBM, so counter / 2^30 is the factor that
@@ -79,5 +81,48 @@ def batched():
         j.free()
 
 
+def c3(iterations: int = 3):
+    """The L=16, T=1, 1024-walker job in the launch shape the benchmark
+    tunes for it (from the committed tuning cache)."""
+    import torch
+
+    from . import MucaJob, autotune, workloads
+
+    w = workloads.workload("l16_t1_w1024")
+    shape = autotune.tune_job(w["L"], w["T"], w["n_walkers"], seed=w["seed"], probe_sweeps=1000,
+                              cache=autotune.CACHE, warm=autotune.BENCH_WARM_PLAIN)
+    job = MucaJob(w["L"], w["T"], w["n_walkers"], seed=w["seed"], max_delta=1)
+    job.set_launch(*shape)
+    print(f"c3 launch {job.get_launch()}", flush=True)
+    for it in range(iterations):
+        job.sweep(w["sweeps"])
+        job.update_weights(job.reduce_hist())
+        print(f"iteration {it} done", flush=True)
+    torch.cuda.synchronize()
+    job.free()
+
+
+def bigL(L: int, walkers: int, packing: int, iterations: int = 3, sweeps: int = 200):
+    """A large lattice with many walkers (one wave per walker, thresholds
+    through the caches), lattices packed or not: 3 iterations of 200 sweeps
+    from a flat start."""
+    import torch
+
+    from . import MucaJob
+
+    job = MucaJob(L, 2.0, walkers, seed=7, max_delta=1)
+    job.set_launch(1, 1, 0, packing)
+    print(f"bigL L={L} walkers={walkers} launch {job.get_launch()}", flush=True)
+    for it in range(iterations):
+        job.sweep(sweeps)
+        job.update_weights(job.reduce_hist())
+        print(f"iteration {it} done", flush=True)
+    torch.cuda.synchronize()
+    job.free()
+
+
 if __name__ == "__main__":
-    {"copy": copy, "sweep": sweep, "saturation": saturation, "batched": batched}[sys.argv[1]]()
+    if sys.argv[1] == "bigL":
+        bigL(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]))
+    else:
+        {"copy": copy, "sweep": sweep, "saturation": saturation, "batched": batched, "c3": c3}[sys.argv[1]]()

@@ -23,7 +23,8 @@ def iterate(jobs, sweep, iterations, sweeps):
     return hists
 
 
-@pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1), (4, 1), (4, 2)])
+@pytest.mark.parametrize("shape", [(0, 1, 0, 0), (0, 2), (1, 1, 0, 0), (1, 2), (2, 1, 0, 0), (4, 1, 0, 0), (4, 2),
+                                   (0, 1, 0, 1), (1, 1, 0, 1), (2, 1, 0, 1), (4, 1, 0, 1)])
 def test_batch_equals_plain(shape):
     print(f"[batch] mixed jobs {MIX} shape {shape}", flush=True)
     a = [MucaJob(L, T, nw, seed=s, max_delta=4) for (L, T, nw, s) in MIX]

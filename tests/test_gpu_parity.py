@@ -260,12 +260,21 @@ def test_truncated_l16_t1_w1024():
 
 
 @pytest.mark.parametrize("wpw", [1, 2, 4])
-@pytest.mark.parametrize("bpl", [1, 2])
+@pytest.mark.parametrize("bpl,packing", [(1, 0), (1, 1), (2, 0)])
 @pytest.mark.parametrize("lds_tables", [0, 1])
-def test_launch_shapes_agree(wpw, bpl, lds_tables):
+def test_launch_shapes_agree(wpw, bpl, packing, lds_tables):
     """Every launch shape replays the same chain (L=6: classes of 108 sites span
-    several lane groups at 1 wave per walker; 7 walkers leave ragged blocks)."""
-    run_both(6, 1.4182, 7, 11, 3, 60, 40, np.linspace(1.0, 3.5, 9), launch=(wpw, bpl, lds_tables))
+    several lane groups at 1 wave per walker; 7 walkers leave ragged blocks),
+    with lattices in LDS as bytes or as 2-bit codes."""
+    run_both(6, 1.4182, 7, 11, 3, 60, 40, np.linspace(1.0, 3.5, 9), launch=(wpw, bpl, lds_tables, packing))
+
+
+@pytest.mark.parametrize("L,wpw,lds_tables", [(5, 1, 1), (9, 2, 0), (12, 4, 1), (16, 1, 0), (24, 4, 0)])
+def test_packed_lattices_agree(L, wpw, lds_tables):
+    """Packed lattices (2-bit codes in LDS) replay the sequential chain at odd
+    L (3-colour classes straddling 4-site blocks), with neighbour positions in
+    registers (few passes per sweep) and read per pass (many), and at L=24."""
+    run_both(L, 1.2, 6, 40 + L, 2, 12, 8, np.linspace(2.5, 3.2, 5), launch=(wpw, 1, lds_tables, 1))
 
 
 @pytest.mark.parametrize("L", [2, 3, 5, 7, 9])

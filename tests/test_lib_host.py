@@ -94,8 +94,10 @@ def test_init_argument_checks_without_device():
     assert lib.muca_reduce_hist(None, None, 0) == -1
     assert lib.muca_update_weights(None, None, None, None) == -1
     assert lib.muca_reweight(None, None, 1, None) == -1
-    assert lib.muca_batch_get_launch(None, None, None, None) == -1
-    assert lib.muca_batch_set_launch(None, 1, 1, 0) == -1
+    assert lib.muca_batch_get_launch(None, None, None, None, None) == -1
+    assert lib.muca_batch_set_launch(None, 1, 1, 0, -1) == -1
+    assert lib.muca_batch_poll(None, None) == -1 and lib.muca_batch_finish(None) == -1
+    assert lib.muca_set_window(None, 0, 1) == -1 and lib.muca_set_stream(None, None) == -1
     assert lib.muca_batch_sweep(None, 1, 0) == -1
     lib.muca_free(None)
     lib.muca_batch_free(None)
