@@ -14,7 +14,8 @@
  *                    expectation values at any Delta.
  *   Eq. (FieldDerivative), Eq. (sph)  field derivatives, C(Delta) = d<E_J>/dDelta.
  *
- * Conventions fixed where the paper is silent (identical in the test oracle):
+ * Conventions fixed where the paper is silent (identical in the test oracle;
+ * the walker index w below is the global one, first_walker + local index):
  *   site i = x + L(y + Lz); colour-major visiting order (even L: colour (x+y+z) mod 2;
  *   odd L: f(t) = t mod 2 for t <= L-2, f(L-1) = 2, colour (f(x)+f(y)+f(z)) mod 3;
  *   colours ascending, then z, y, x ascending); proposal = the b-th (ascending) of the
@@ -71,6 +72,11 @@ typedef struct {
     int32_t n_walkers; /* >= 1 independent walkers sharing one weight function */
     uint64_t seed;     /* Philox key: k0 = low 32 bits, k1 = high 32 bits */
     int32_t max_delta; /* largest n_delta a muca_reweight call may ask for, 0..65536 */
+    int32_t first_walker; /* global index of the job's walker 0 (>= 0): the job holds walkers
+                             [first_walker, first_walker + n_walkers) of a larger run with the same
+                             seed, so a run split into such sub-jobs (one per device, say) replays
+                             exactly the chains of the whole run and its merged histogram is the sum
+                             of theirs; 0 for a whole job */
 } muca_params;
 
 /* Caller-owned device buffers, sized by muca_query_sizes (bytes, 256-aligned). */
@@ -167,6 +173,16 @@ int muca_set_recursion(muca_job *job, uint32_t flags);
  * earlier run, a checkpoint, or a start tilted towards some Delta. */
 int muca_set_weights(muca_job *job, const double *lnW);
 
+/* State of the weight recursion, for an exact checkpoint of a job iterating
+ * with MUCA_REC_ACCUMULATED or MUCA_REC_EXTRAPOLATE: kacc (V doubles, the
+ * accumulated pair weights) and seen (V+1 bytes, 1 for the bins any iteration
+ * since muca_set_recursion has reached).  get copies them out; set restores
+ * them (after muca_set_recursion, muca_set_window and muca_set_weights, which
+ * reset them).  Either pointer may be NULL (not copied).  MUCA_E_INVAL on a
+ * negative or non-finite kacc or a seen byte other than 0 or 1. */
+int muca_get_recursion_state(const muca_job *job, double *kacc, uint8_t *seen);
+int muca_set_recursion_state(muca_job *job, const double *kacc, const uint8_t *seen);
+
 /* Copy the job's current weights (V+1 doubles) to lnW_out. */
 int muca_get_weights(const muca_job *job, double *lnW_out);
 
@@ -246,6 +262,11 @@ int muca_read_accum(muca_job *job, int64_t *sums, uint64_t *sm4);
 
 /* Zero the production sums.  Asynchronous. */
 int muca_reset_accum(muca_job *job);
+
+/* Overwrite the production sums from the host (checkpoint resume), in the
+ * layout muca_read_accum returns; marks them as recorded when they hold any
+ * measurement.  Synchronises. */
+int muca_write_accum(muca_job *job, const int64_t *sums, const uint64_t *sm4);
 
 /* Launch shape of the sweep kernel (results do not depend on it):
  * waves_per_walker in {1, 2, 4} (64, 128 or 256 lanes cooperate on one walker),

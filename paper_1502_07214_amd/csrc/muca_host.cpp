@@ -73,6 +73,7 @@ bool params_ok(const muca_params *p)
     if (!(p->T > 0.0)) return false;  // rejects NaN and T <= 0; +inf allowed
     if (p->n_walkers < 1) return false;
     if (p->max_delta < 0 || p->max_delta > 65536) return false;
+    if (p->first_walker < 0 || (int64_t)p->first_walker + p->n_walkers > ((int64_t)1 << 31)) return false;
     return true;
 }
 
@@ -471,6 +472,7 @@ int muca_init(const muca_params *params, const muca_dev_buffers *buffers, const 
     ia.n_walkers = g.n_walkers;
     ia.k0 = j->k0;
     ia.k1 = j->k1;
+    ia.w0 = params->first_walker;
     if ((e = launch_init(ia, j->stream)) != hipSuccess) return bail(fail_device(e, "init kernels"));
     if ((e = hipStreamSynchronize(j->stream)) != hipSuccess) return bail(fail_device(e, "hipStreamSynchronize"));
     default_launch(j);
@@ -509,6 +511,7 @@ int muca_sweep(muca_job *j, int64_t n_sweeps, uint32_t flags)
     a.k1 = j->k1;
     a.rec_lo = j->win_lo;
     a.rec_hi = j->win_hi;
+    a.w0 = j->p.first_walker;
     a.lds_hist = pl.lds_hist ? 1 : 0;
     a.lds_off_hist = pl.off_hist;
     a.lds_off_lat = pl.off_lat;
@@ -682,6 +685,29 @@ int muca_get_window(const muca_job *j, int32_t *lo, int32_t *hi)
     return MUCA_OK;
 }
 
+int muca_get_recursion_state(const muca_job *j, double *kacc, uint8_t *seen)
+{
+    if (!j) return MUCA_E_INVAL;
+    if (kacc) std::memcpy(kacc, j->kacc.data(), sizeof(double) * (size_t)j->g.V);
+    if (seen) std::memcpy(seen, j->seen.data(), (size_t)j->g.V + 1);
+    return MUCA_OK;
+}
+
+int muca_set_recursion_state(muca_job *j, const double *kacc, const uint8_t *seen)
+{
+    if (!j) return MUCA_E_INVAL;
+    const int V = j->g.V;
+    if (kacc)
+        for (int E = 0; E < V; ++E)
+            if (!std::isfinite(kacc[E]) || kacc[E] < 0.0) return MUCA_E_INVAL;
+    if (seen)
+        for (int E = 0; E <= V; ++E)
+            if (seen[E] > 1) return MUCA_E_INVAL;
+    if (kacc) std::memcpy(j->kacc.data(), kacc, sizeof(double) * (size_t)V);
+    if (seen) std::memcpy(j->seen.data(), seen, (size_t)V + 1);
+    return MUCA_OK;
+}
+
 int muca_get_weights(const muca_job *j, double *lnW_out)
 {
     if (!j || !lnW_out) return MUCA_E_INVAL;
@@ -849,6 +875,25 @@ int muca_read_accum(muca_job *j, int64_t *sums, uint64_t *sm4)
     HIP_TRY(hipStreamSynchronize(j->stream));
     if (sums) std::memcpy(sums, buf.data(), 5 * V1 * 8);
     if (sm4) std::memcpy(sm4, buf.data() + 5 * V1, 2 * V1 * 8);
+    return MUCA_OK;
+}
+
+int muca_write_accum(muca_job *j, const int64_t *sums, const uint64_t *sm4)
+{
+    if (!j || !sums || !sm4) return MUCA_E_INVAL;
+    const size_t V1 = (size_t)j->g.V + 1;
+    int64_t n = 0;
+    for (size_t E = 0; E < V1; ++E) {
+        if (sums[E] < 0) return MUCA_E_INVAL;
+        n += sums[E];
+    }
+    if (int rc = use_device(j)) return rc;
+    std::vector<uint64_t> buf(7 * V1);
+    std::memcpy(buf.data(), sums, 5 * V1 * 8);
+    std::memcpy(buf.data() + 5 * V1, sm4, 2 * V1 * 8);
+    HIP_TRY(hipMemcpyAsync(j->d.accum, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, j->stream));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    j->recorded = n > 0 ? 1 : 0;
     return MUCA_OK;
 }
 
@@ -1068,6 +1113,7 @@ int fill_batch(const BatchPlan &p, const int *order, BatchJob *bj, int2 *tiles)
         J.k1 = j->k1;
         J.rec_lo = j->win_lo;
         J.rec_hi = j->win_hi;
+        J.w0 = j->p.first_walker;
         J.lds_tables = p.tab_bytes > 0 && job_tab_bytes(j) <= p.tab_bytes ? 1 : 0;
         J.wpw = p.wpw_of(k);
     }

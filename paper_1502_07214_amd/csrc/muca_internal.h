@@ -47,6 +47,7 @@ struct SweepArgs {
     unsigned pass_sync;            // bit k: synchronise after pass k (end of a colour class)
     uint32_t k0, k1;
     int rec_lo, rec_hi;            // production sums record only E_Delta in [rec_lo, rec_hi]
+    int w0;                        // global index of walker 0 (Philox counter word 1)
     int n_sweeps;
     int lds_hist;                  // 1: histogram in LDS, flushed at the end
     int lds_off_hist, lds_off_lat, lds_off_r, lds_off_nb;
@@ -59,6 +60,7 @@ struct InitArgs {
     const uint16_t *site;
     int V, Vp, n_walkers;
     uint32_t k0, k1;
+    int w0;                          // global index of walker 0
 };
 
 struct LogHistArgs {
@@ -93,6 +95,7 @@ struct BatchJob {
     int cls[kMaxClasses + 1];
     uint32_t k0, k1;
     int rec_lo, rec_hi;      // production sums record only E_Delta in [rec_lo, rec_hi]
+    int w0;                  // global index of walker 0
     int lds_tables;          // 1: thresholds and neighbour table staged in LDS for this job's tiles
     int wpw;                 // waves per walker of this job's tiles (1 or 4) in a per-job launch
 };

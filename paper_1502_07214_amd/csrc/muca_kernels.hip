@@ -469,7 +469,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     wk.sBp = sBp;
     wk.sX = sX;
     wk.V = V;
-    wk.w32 = (uint32_t)walker;
+    wk.w32 = (uint32_t)(a.w0 + walker);  // the global walker index keys the chain
     wk.k0 = a.k0;
     wk.k1 = a.k1;
     wk.myEJ = 0u;
@@ -683,6 +683,7 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
         a.k1 = J.k1;
         a.rec_lo = J.rec_lo;
         a.rec_hi = J.rec_hi;
+        a.w0 = J.w0;
         a.n_sweeps = b.n_sweeps;
         a.lds_hist = 0;
         a.lds_off_hist = kLdsFixed;
@@ -700,7 +701,8 @@ __global__ __launch_bounds__(kBlock) void muca_batch_kernel(BatchArgs b)
 
 // ---------------------------------------------------------------------------
 // Initial lattices: spin at position p (site i = site[p]) from word i&3 of the
-// Philox block (i>>2, w, 0, 1): s = floor(3 x / 2^32) - 1.  Padding bytes are 0.
+// Philox block (i>>2, w, 0, 1), w the global walker index: s = floor(3 x / 2^32) - 1.
+// Padding bytes are 0.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void muca_init_lattice_kernel(InitArgs a)
 {
@@ -711,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void muca_init_lattice_kernel(InitArgs a)
     int v = 0;
     if (p < a.V) {
         const int i = a.site[p];
-        const Ctr4 x = philox10((uint32_t)(i >> 2), (uint32_t)w, 0u, 1u, a.k0, a.k1);
+        const Ctr4 x = philox10((uint32_t)(i >> 2), (uint32_t)(a.w0 + w), 0u, 1u, a.k0, a.k1);
         const uint32_t xw = x.v[i & 3];
         v = (int)(((uint64_t)xw * 3u) >> 32) - 1;
     }

@@ -32,7 +32,8 @@ EXPORTS = (
     "muca_batch_set_launch", "muca_batch_get_launch", "muca_batch_sweep", "muca_batch_free", "muca_flatness", "muca_reweight_sums",
     "muca_reweight_hist", "muca_reweight_hist_sums", "muca_set_recursion", "muca_batch_sweep_static",
     "muca_set_window", "muca_get_window", "muca_host_walls", "muca_batch_submit", "muca_batch_poll",
-    "muca_batch_finish", "muca_set_stream",
+    "muca_batch_finish", "muca_set_stream", "muca_get_recursion_state", "muca_set_recursion_state",
+    "muca_write_accum",
 )
 
 # weight recursion flags (muca_set_recursion)
@@ -49,7 +50,7 @@ class MucaError(RuntimeError):
 
 class muca_params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("T", ctypes.c_double), ("n_walkers", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("max_delta", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("max_delta", ctypes.c_int32), ("first_walker", ctypes.c_int32)]
 
 
 class muca_dev_buffers(ctypes.Structure):
@@ -91,6 +92,9 @@ def lib():
     L.muca_host_walls.argtypes = [i32, dbl, i32, i32, P(dbl)]
     L.muca_set_window.argtypes = [vp, i32, i32]
     L.muca_set_stream.argtypes = [vp, vp]
+    L.muca_get_recursion_state.argtypes = [vp, P(dbl), P(ctypes.c_uint8)]
+    L.muca_set_recursion_state.argtypes = [vp, P(dbl), P(ctypes.c_uint8)]
+    L.muca_write_accum.argtypes = [vp, P(i64), P(ctypes.c_uint64)]
     L.muca_get_window.argtypes = [vp, P(i32), P(i32)]
     L.muca_host_order.argtypes = [i32, P(i32)]
     L.muca_strerror.argtypes = [ctypes.c_int]
@@ -129,13 +133,15 @@ def _p(a: np.ndarray, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-def _params(L, T, n_walkers, seed, max_delta) -> muca_params:
-    return muca_params(int(L), float(T), int(n_walkers), int(seed) & 0xFFFFFFFFFFFFFFFF, int(max_delta))
+def _params(L, T, n_walkers, seed, max_delta, first_walker=0) -> muca_params:
+    return muca_params(int(L), float(T), int(n_walkers), int(seed) & 0xFFFFFFFFFFFFFFFF, int(max_delta),
+                       int(first_walker))
 
 
-def muca_query_sizes(L: int, T: float, n_walkers: int, seed: int = 0, max_delta: int = 0) -> dict:
+def muca_query_sizes(L: int, T: float, n_walkers: int, seed: int = 0, max_delta: int = 0,
+                     first_walker: int = 0) -> dict:
     s = [ctypes.c_size_t() for _ in range(6)]
-    pr = _params(L, T, n_walkers, seed, max_delta)
+    pr = _params(L, T, n_walkers, seed, max_delta, first_walker)
     _check(lib().muca_query_sizes(ctypes.byref(pr), *[ctypes.byref(x) for x in s]), "muca_query_sizes")
     return dict(zip(("lattice", "walker_state", "hist", "tables", "accum", "obs"), [x.value for x in s]))
 
@@ -179,7 +185,7 @@ class MucaJob:
     `stream` (a torch.cuda.Stream, default: the device's current stream)."""
 
     def __init__(self, L: int, T: float, n_walkers: int, seed: int = 0, lnW: Optional[Sequence[float]] = None,
-                 max_delta: int = 256, device=None, stream=None):
+                 max_delta: int = 256, device=None, stream=None, first_walker: int = 0):
         import torch
 
         self.L, self.V, self.T = int(L), int(L) ** 3, float(T)
@@ -188,7 +194,7 @@ class MucaJob:
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        sizes = muca_query_sizes(L, T, n_walkers, seed, max_delta)
+        sizes = muca_query_sizes(L, T, n_walkers, seed, max_delta, first_walker)
         self.sizes = sizes
         self._tensors = {}
         ptrs = {}
@@ -199,7 +205,8 @@ class MucaJob:
             ptrs[name] = t.data_ptr() + off
         self.buffers = muca_dev_buffers(**ptrs)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        pr = _params(L, T, n_walkers, seed, max_delta)
+        self.first_walker = int(first_walker)
+        pr = _params(L, T, n_walkers, seed, max_delta, first_walker)
         lw = None
         if lnW is not None:
             lw = np.ascontiguousarray(lnW, dtype=np.float64)
@@ -335,6 +342,30 @@ class MucaJob:
 
     def reset_accum(self):
         _check(lib().muca_reset_accum(self._h), "muca_reset_accum")
+
+    def write_accum(self, sums: dict):
+        """Restore production sums given as exact integers (the read_accum format)."""
+        V1 = self.V + 1
+        s5 = np.array([[int(v) for v in sums[k]] for k in ("H", "SJ", "SJJ", "SA", "SM2")], dtype=np.int64)
+        m4 = [int(v) for v in sums["SM4"]]
+        sm4 = np.array([[v & 0xFFFFFFFFFFFFFFFF for v in m4], [v >> 64 for v in m4]], dtype=np.uint64)
+        assert s5.shape == (5, V1)
+        _check(lib().muca_write_accum(self._h, _p(s5, ctypes.c_int64), _p(sm4, ctypes.c_uint64)), "muca_write_accum")
+
+    def recursion_state(self):
+        """(kacc, seen) of the weight recursion, for an exact checkpoint."""
+        kacc = np.zeros(self.V, dtype=np.float64)
+        seen = np.zeros(self.V + 1, dtype=np.uint8)
+        _check(lib().muca_get_recursion_state(self._h, _p(kacc, ctypes.c_double), _p(seen, ctypes.c_uint8)),
+               "muca_get_recursion_state")
+        return kacc, seen
+
+    def set_recursion_state(self, kacc, seen):
+        k = np.ascontiguousarray(kacc, dtype=np.float64)
+        sn = np.ascontiguousarray(seen, dtype=np.uint8)
+        assert k.shape == (self.V,) and sn.shape == (self.V + 1,)
+        _check(lib().muca_set_recursion_state(self._h, _p(k, ctypes.c_double), _p(sn, ctypes.c_uint8)),
+               "muca_set_recursion_state")
 
     def set_stats(self, enable: bool = True):
         _check(lib().muca_set_stats(self._h, 1 if enable else 0), "muca_set_stats")

@@ -343,21 +343,102 @@ def test_checkpoint_resume_bit_exact():
     b.free()
 
 
-def test_walker_split_equals_whole():
-    """Sharding: walkers split into groups (separate jobs holding walker ranges
-    are not expressible, so split by running the same job twice and summing is
-    replaced by the histogram identity over walker subsets via the oracle)."""
-    L, T, nw = 5, 2.0, 6
-    job = MucaJob(L, T, nw, seed=12, max_delta=1)
-    job.sweep(25)
-    h = job.reduce_hist()
-    parts = []
-    for first, n in ((0, 2), (2, 3), (5, 1)):
-        o = oracle.OracleJob(L, T, n, 12, first_walker=first)
-        o.sweep(25)
-        parts.append(o.take_hist())
-    assert np.array_equal(h, sum(parts))
-    job.free()
+@pytest.mark.parametrize("batched", [False, True])
+def test_walker_split_equals_whole(batched):
+    """Sharding over walkers (one sub-job per device, say): sub-jobs holding
+    walker ranges [first, first + n) of the same seed, each updating its
+    weights with the sum of all sub-jobs' histograms (what an all-reduce
+    gives), replay the whole job exactly: merged histograms, weights, and
+    every walker's lattice and energies, over several iterations; the sub-jobs
+    swept one by one or in one batched launch."""
+    L, T, nw, seed = 7, 1.4182, 11, 12
+    ranges = ((0, 3), (3, 5), (8, 1), (9, 2))
+    say(f"[parity] walker split L={L} walkers={nw} ranges={ranges} batched={batched}")
+    whole = MucaJob(L, T, nw, seed=seed, max_delta=1)
+    subs = [MucaJob(L, T, n, seed=seed, max_delta=1, first_walker=f) for f, n in ranges]
+    batch = MucaBatch(subs) if batched else None
+    for it in range(4):
+        whole.sweep(30)
+        if batch is not None:
+            batch.sweep(30)
+        else:
+            for j in subs:
+                j.sweep(30)
+        h = whole.reduce_hist()
+        merged = sum(j.reduce_hist() for j in subs)
+        assert np.array_equal(h, merged), f"iteration {it}"
+        whole.update_weights(h)
+        for j in subs:
+            j.update_weights(merged)
+            assert j.lnW.tobytes() == whole.lnW.tobytes()
+    spins, state = whole.read_state()
+    for (f, n), j in zip(ranges, subs):
+        sp, st = j.read_state()
+        assert np.array_equal(sp, spins[f:f + n]) and np.array_equal(st, state[f:f + n])
+    if batch is not None:
+        batch.free()
+    for j in subs + [whole]:
+        j.free()
+
+
+def test_first_walker_against_oracle():
+    """A sub-job's walkers are the oracle's walkers of the same global indices."""
+    L, T, seed, f, n = 5, 2.0, 33, 1000, 4
+    j = MucaJob(L, T, n, seed=seed, max_delta=1, first_walker=f)
+    o = oracle.OracleJob(L, T, n, seed, first_walker=f)
+    sp, st = j.read_state()
+    assert np.array_equal(sp, o.spins) and np.array_equal(st, o.state)
+    j.sweep(20)
+    o.sweep(20)
+    assert np.array_equal(j.reduce_hist(), o.take_hist())
+    sp, st = j.read_state()
+    assert np.array_equal(sp, o.spins) and np.array_equal(st, o.state)
+    j.free()
+
+
+def test_checkpoint_resume_accumulated_recursion_and_production():
+    """An exact checkpoint under the accumulated + extrapolating recursion
+    restores walkers, weights, the recursion's pair weights and visited bins,
+    and the production sums recorded so far: the resumed job continues bit for
+    bit like the original."""
+    L, T, nw, seed = 6, 1.2, 8, 19
+    a = MucaJob(L, T, nw, seed=seed, max_delta=4)
+    a.set_recursion(3)
+    for _ in range(3):
+        a.sweep(40)
+        a.update_weights(a.reduce_hist())
+    a.sweep(30, record=True)
+    a.reduce_hist()
+    spins, state = a.read_state()
+    lnW, (kacc, seen), sums = a.lnW, a.recursion_state(), a.read_accum()
+    assert kacc.max() > 0 and seen.sum() > 0
+    a.sweep(30, record=True)
+    a.reduce_hist()
+    final_sums = a.read_accum()
+    for _ in range(2):
+        a.sweep(40)
+        a.update_weights(a.reduce_hist())
+    b = MucaJob(L, T, nw, seed=seed, max_delta=4)
+    b.set_recursion(3)
+    b.write_state(spins, state)
+    b.set_weights(lnW)
+    b.set_recursion_state(kacc, seen)
+    b.write_accum(sums)
+    b.sweep(30, record=True)
+    b.reduce_hist()
+    assert b.read_accum() == final_sums
+    for _ in range(2):
+        b.sweep(40)
+        b.update_weights(b.reduce_hist())
+    assert a.lnW.tobytes() == b.lnW.tobytes()
+    sa, sta = a.read_state()
+    sb, stb = b.read_state()
+    assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+    ka, na = a.recursion_state()
+    kb, nb = b.recursion_state()
+    assert ka.tobytes() == kb.tobytes() and np.array_equal(na, nb)
+    a.free()
+    b.free()
 
 
 @pytest.mark.parametrize("wpw", [1, 2, 4])

@@ -71,7 +71,7 @@ def test_query_sizes():
 @pytest.mark.parametrize("args", [
     (1, 2.0, 4, 0, 0), (33, 2.0, 4, 0, 0), (4, 0.0, 4, 0, 0), (4, -1.0, 4, 0, 0),
     (4, float("nan"), 4, 0, 0), (4, 2.0, 0, 0, 0), (4, 2.0, -3, 0, 0), (4, 2.0, 4, 0, -1),
-    (4, 2.0, 4, 0, 70000),
+    (4, 2.0, 4, 0, 70000), (4, 2.0, 4, 0, 0, -1), (4, 2.0, 4, 0, 0, 2 ** 31 - 2),
 ])
 def test_invalid_params_rejected(args):
     with pytest.raises(muca.MucaError) as e:
@@ -81,7 +81,7 @@ def test_invalid_params_rejected(args):
 
 def test_init_argument_checks_without_device():
     lib = muca.lib()
-    pr = muca.muca_params(4, 2.0, 4, 0, 8)
+    pr = muca.muca_params(4, 2.0, 4, 0, 8, 0)
     h = ctypes.c_void_p()
     bufs = muca.muca_dev_buffers(None, None, None, None, None, None)
     assert lib.muca_init(ctypes.byref(pr), ctypes.byref(bufs), None, None, ctypes.byref(h)) == -1
