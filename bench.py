@@ -284,28 +284,40 @@ def convergence_leg():
     return out
 
 
-def saturation_leg(launch_ms_out=None):
+def saturation_run(L, T, n_walkers, seed, sweeps):
+    """One saturation job: 10 untimed sweeps, then one launch of `sweeps`
+    timed with HIP events on the job's stream, in the library's launch shape."""
     import torch
 
-    from paper_1502_07214_amd import MucaJob, workloads
+    from paper_1502_07214_amd import MucaJob
 
-    s = workloads.SATURATION
-    job = MucaJob(s["L"], s["T"], s["n_walkers"], seed=s["seed"], max_delta=1)
+    job = MucaJob(L, T, n_walkers, seed=seed, max_delta=1)
     job.sweep(10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    job.sweep(s["sweeps"])
+    job.sweep(sweeps)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    rate = s["n_walkers"] * s["L"] ** 3 * s["sweeps"] / (ms * 1e-3)
+    rate = n_walkers * L ** 3 * sweeps / (ms * 1e-3)
     shape = job.get_launch()
     job.free()
-    return {"workload": f"L={s['L']} T={s['T']} walkers={s['n_walkers']} sweeps={s['sweeps']}", "launch": shape,
+    return {"workload": f"L={L} T={T} walkers={n_walkers} sweeps={sweeps}", "launch": shape,
             "kernel_attempts_per_s": rate, "launch_ms": ms,
             "roofline_frac": rate * ALGO_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S,
             "roofline_frac_itemised": rate * ITEMISED_SLOTS_PER_ATTEMPT / PEAK_SLOTS_PER_S}
+
+
+def saturation_leg():
+    """The saturation job (L=8, 65 536 walkers), and the grid over L = 8, 12,
+    16 and 1, 2, 4 waves of walkers per SIMD."""
+    from paper_1502_07214_amd import workloads
+
+    s = workloads.SATURATION
+    out = saturation_run(s["L"], s["T"], s["n_walkers"], s["seed"], s["sweeps"])
+    out["grid"] = [saturation_run(L, s["T"], n, s["seed"], s["sweeps"]) for (L, n) in workloads.SATURATION_GRID]
+    return out
 
 
 def cpu_baseline(w, deltas):
@@ -400,6 +412,7 @@ def main():
                    "iterations": w["iterations"], "sweeps_per_iteration": w["sweeps"],
                    "production_sweeps": w["production"], "n_delta": len(deltas), "launch": shape},
         "kernel_attempts_per_s": kernel_rate,
+        "per_walker_attempts_per_s": kernel_rate / w["n_walkers"],
         "sweep_launch_ms": launch_ms,
         "final_flatness": flat,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,

@@ -3,6 +3,7 @@
     python -m paper_1502_07214_amd.profile_runs copy    # plain device copy of 1 GiB, 3 times
     python -m paper_1502_07214_amd.profile_runs sweep   # the benchmark's sweep launches (L=12, 256 walkers)
     python -m paper_1502_07214_amd.profile_runs saturation  # L=8, 65 536 walkers, 10 + 100 sweeps
+    python -m paper_1502_07214_amd.profile_runs satgrid     # L=8, 12, 16 x 65 536 .. 262 144 walkers, 10 + 100 sweeps
     python -m paper_1502_07214_amd.profile_runs batched     # 19 mixed jobs: 10 batched launches of 1000 sweeps
     python -m paper_1502_07214_amd.profile_runs c3          # L=16, T=1, 1024 walkers: 3 iterations of 2*10^4 sweeps
     python -m paper_1502_07214_amd.profile_runs bigL L W P  # L^3, W walkers, packing P (0, 1, -1 auto): 3 x 200 sweeps
@@ -60,6 +61,24 @@ def saturation():
     torch.cuda.synchronize()
     print(f"saturation: {s['n_walkers']} walkers at L={s['L']}, 10 + {s['sweeps']} sweeps", flush=True)
     job.free()
+
+
+def saturation_grid():
+    """The saturation grid: L = 8, 12, 16 with 65 536, 131 072 and 262 144
+    walkers (flat weights, T = 2), each 10 + 100 sweeps in the library's
+    launch shape, in the grid's order."""
+    import torch
+
+    from . import MucaJob, workloads
+
+    s = workloads.SATURATION
+    for (L, n) in workloads.SATURATION_GRID:
+        job = MucaJob(L, s["T"], n, seed=s["seed"], max_delta=1)
+        job.sweep(10)
+        job.sweep(s["sweeps"])
+        torch.cuda.synchronize()
+        print(f"saturation grid: L={L} walkers={n} launch {job.get_launch()}, 10 + {s['sweeps']} sweeps", flush=True)
+        job.free()
 
 
 def batched():
@@ -125,4 +144,5 @@ if __name__ == "__main__":
     if sys.argv[1] == "bigL":
         bigL(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]))
     else:
-        {"copy": copy, "sweep": sweep, "saturation": saturation, "batched": batched, "c3": c3}[sys.argv[1]]()
+        {"copy": copy, "sweep": sweep, "saturation": saturation, "satgrid": saturation_grid, "batched": batched,
+         "c3": c3}[sys.argv[1]]()

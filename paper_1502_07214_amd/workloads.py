@@ -88,6 +88,9 @@ BATCHED_LANES = (8, 10, 12, 16)
 
 # Saturation: enough walkers to fill every SIMD several times over (roofline run).
 SATURATION = dict(L=8, T=2.0, n_walkers=65536, seed=0, sweeps=100)
+# The saturation runs over lattice sizes and walker counts: 1024 SIMDs x 64
+# lanes x 1, 2, 4 waves of walkers at L = 8, 12, 16 (flat weights, T = 2).
+SATURATION_GRID = tuple((L, n) for L in (8, 12, 16) for n in (65536, 131072, 262144))
 
 # Time to a flat histogram (min/mean > 0.5 over [0, V]) for single jobs, with
 # the plain recursion and with the accumulated + extrapolating one, from a flat

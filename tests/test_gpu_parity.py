@@ -252,6 +252,33 @@ def test_saturation_job_sampled():
     job.free()
 
 
+@pytest.mark.parametrize("L,nw", [(12, 131072), (16, 262144)])
+def test_saturation_grid_sampled(L, nw):
+    """Saturation runs of the grid at full size in the library's launch shape
+    (10 + 20 sweeps under flat weights at T = 2): sampled walkers, the first
+    and last among them, replayed on the oracle end bit-identical; sampled
+    walkers' energies equal a recomputation; the histogram counts every sweep
+    of every walker."""
+    s = workloads.SATURATION
+    assert (L, nw) in workloads.SATURATION_GRID
+    say(f"[parity] saturation grid L={L} walkers={nw}")
+    job = MucaJob(L, s["T"], nw, seed=s["seed"], max_delta=1)
+    job.sweep(10)
+    job.sweep(20)
+    h = job.reduce_hist(reset=True)
+    assert h.sum() == nw * 30
+    spins, state = job.read_state()
+    assert np.all(state[:, 3] == 30)
+    for w in range(0, nw, 4099):
+        assert oracle.energies(L, spins[w]) == tuple(int(v) for v in state[w, :3]), f"walker {w}"
+    for w in (0, 65537, nw - 1):
+        o = oracle.OracleJob(L, s["T"], 1, s["seed"], first_walker=w)
+        o.sweep(10)
+        o.sweep(20)
+        assert np.array_equal(o.spins[0], spins[w]) and np.array_equal(o.state[0], state[w]), f"walker {w}"
+    job.free()
+
+
 def test_truncated_l16_t1_w1024():
     """L=16, T=1.0, all 1024 walkers, 2 iterations x 100 sweeps + 100 production."""
     w = workloads.workload("l16_t1_w1024", truncated=True)
