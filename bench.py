@@ -180,7 +180,8 @@ def served_leg():
     reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"],
                             delta_halfwidth=sp["delta_halfwidth"])
     cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"],
-                      wall_budget=sp["wall_budget"], recursion=REC_ACC_EXT, lane_bounds=tuple(sp["lane_bounds"]))
+                      wall_budget=sp["wall_budget"], recursion=REC_ACC_EXT, lane_bounds=tuple(sp["lane_bounds"]),
+                      entries_per_bin=sp["entries_per_bin"])
     out = {"spec": {k: v for k, v in sp.items()}, "recursion": "accumulated+extrapolate"}
     modes = (("served_async", serve, cfg), ("served_lockstep", serve, dataclasses.replace(cfg, lane_bounds=())),
              ("one_at_a_time", serve_plain, cfg))
@@ -190,7 +191,7 @@ def served_leg():
         out[mode] = {k: r[k] for k in ("jobs", "converged", "censored", "not_arrived", "makespan_s", "converged_per_s",
                                        "attempts_per_s", "latency_p50_s", "latency_p99_s",
                                        "latency_converged_p50_s", "latency_converged_p99_s", "iterations_p50",
-                                       "queue_depth_max")}
+                                       "long_iteration_jobs", "queue_depth_max")}
     return out
 
 

@@ -167,6 +167,7 @@ class JobRecord:
     converged: bool = False
     attempts: int = 0
     window: Tuple[int, int] = (0, 0)
+    span: int = 1  # launches per iteration at the end
 
     @property
     def latency(self) -> float:
@@ -189,6 +190,31 @@ class ServeConfig:
     # batch on its own stream and iterates on its own.  () = one lane: every
     # resident job advances one iteration per launch (lock-step).
     lane_bounds: Tuple[int, ...] = ()
+    # Iteration length: an iteration is one launch of `sweeps` sweeps until
+    # the job's histogram has visited every bin of its window; from then on
+    # it spans enough launches to record about entries_per_bin entries per
+    # window bin (0: always one launch).  See iteration_span.
+    entries_per_bin: int = 0
+
+
+def iteration_span(hist: np.ndarray, lo: int, hi: int, n_walkers: int, sweeps: int, entries_per_bin: int) -> int:
+    """Launches of `sweeps` sweeps per iteration after an iteration whose
+    histogram is `hist`.
+
+    Reading (the paper fixes no iteration length): the flatness test
+    min/mean > threshold is taken on one iteration's histogram, so counting
+    noise alone bounds what it can show.  With n entries per bin on average
+    and weights already flat, the least-visited of B bins holds about
+    n - sqrt(2 n ln B) (Poisson), so at 500 sweeps of a few hundred walkers
+    over thousands of bins (tens of entries per bin) the test fails about as
+    often as it passes whatever the weights.  Once every bin of the window
+    has been visited the weights are close enough that longer iterations
+    only sharpen the test, and the iteration is stretched to about
+    entries_per_bin entries per bin; before that, short iterations let the
+    recursion move the weights quickly."""
+    if entries_per_bin <= 0 or not np.all(hist[lo:hi + 1] > 0):
+        return 1
+    return max(1, math.ceil(entries_per_bin * (hi - lo + 1) / (n_walkers * sweeps)))
 
 
 class _Live:
@@ -207,20 +233,31 @@ class _Live:
             self.job.set_stream(stream)
         rec.window = (self.lo, self.hi)
         rec.admitted = now
+        self.span = 1      # launches per iteration
+        self.launches = 0  # launches of the iteration in progress
 
     def step_done(self, cfg: ServeConfig, now: float) -> bool:
-        """Merge the iteration's histogram; finish or update the weights."""
+        """After a launch: at the end of an iteration, merge its histogram
+        (the device histogram accumulates over the iteration's launches) and
+        finish the job or update its weights."""
+        rec = self.rec
+        rec.attempts += rec.req.n_walkers * self.V * cfg.sweeps
+        self.launches += 1
+        if self.launches < self.span:
+            return False
+        self.launches = 0
         h = self.job.reduce_hist(reset=True)
         f = muca_flatness(h, self.lo, self.hi)
-        rec = self.rec
         rec.iterations += 1
         rec.flatness.append(f)
-        rec.attempts += rec.req.n_walkers * self.V * cfg.sweeps
         if f > cfg.threshold or rec.iterations >= cfg.max_iterations:
             rec.converged = f > cfg.threshold
             rec.finished = now
             return True
         self.job.update_weights(h)
+        if self.span == 1:
+            self.span = rec.span = iteration_span(h, self.lo, self.hi, rec.req.n_walkers, cfg.sweeps,
+                                                  cfg.entries_per_bin)
         return False
 
 
@@ -471,6 +508,7 @@ def _summary(records, makespan, attempts, launches, depth, kept) -> dict:
         "latency_converged_p50_s": float(np.percentile([r.latency for r in conv], 50)) if conv else math.nan,
         "latency_converged_p99_s": float(np.percentile([r.latency for r in conv], 99)) if conv else math.nan,
         "iterations_p50": float(np.percentile([r.iterations for r in records.values()], 50)) if records else 0,
+        "long_iteration_jobs": sum(1 for r in records.values() if r.span > 1),
         "queue_depth_max": int(max(depth)) if depth else 0,
         "queue_depth_mean": float(np.mean(depth)) if depth else 0.0,
         "records": records,

@@ -80,7 +80,8 @@ def batched_jobs(spec=BATCHED) -> list:
 # then are censored at it.  Lanes: L <= 12, <= 16, <= 20, larger.
 SERVED = dict(n_jobs=200, rate=20.0, seed=0, L_range=(8, 24), T_range=(0.9, 2.0),
               walker_choices=(64, 128, 192, 256, 320, 384, 448, 512), delta_halfwidth=0.1, sweeps=500,
-              threshold=0.5, max_iterations=2000, wall_budget=40.0, lane_bounds=(12, 16, 20))
+              threshold=0.5, max_iterations=2000, wall_budget=40.0, lane_bounds=(12, 16, 20),
+              entries_per_bin=200)
 
 # Lanes of the batched workload when its jobs iterate asynchronously (L <= 8,
 # 10, 12, 16, larger).

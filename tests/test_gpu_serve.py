@@ -100,6 +100,39 @@ def test_large_windowed_jobs_served_equal_alone(lane_bounds):
         j.free()
 
 
+def test_long_iterations_served_equal_alone():
+    """Iterations stretched once a job's histogram covers its window (here to
+    about 120 entries per window bin: several launches of 40 sweeps per
+    iteration) keep served == alone bit for bit, in asynchronous lanes, and
+    a job that stretched its iterations merges only at their ends."""
+    reqs = [Request(0, 6, 1.2, 64, 201, 0.0, (2.8, 3.0)), Request(1, 7, 2.0, 64, 202, 0.0, (2.42, 2.62)),
+            Request(2, 8, 1.4182, 128, 203, 0.01, (2.7446, 2.9446)), Request(3, 10, 1.0, 64, 204, 0.02, (2.85, 3.05))]
+    cfg = ServeConfig(sweeps=40, threshold=0.99, max_iterations=6, max_walkers=1024, lane_bounds=(7,),
+                      entries_per_bin=120)
+    print("[serve] stretched iterations, L=6..10 mix", flush=True)
+    mix = serve(reqs, cfg, keep_jobs=True)
+    assert any(a.span > 1 for a in mix["records"].values())
+    assert mix["long_iteration_jobs"] == sum(1 for a in mix["records"].values() if a.span > 1)
+    for r in reqs:
+        a = mix["records"][r.id]
+        alone = serve_plain([dataclasses.replace(r, arrival=0.0)], cfg, keep_jobs=True)
+        b = alone["records"][r.id]
+        print(f"[serve] L={r.L} window {a.window} span {a.span} iterations {a.iterations}", flush=True)
+        assert (a.window, a.span, a.iterations, a.flatness) == (b.window, b.span, b.iterations, b.flatness)
+        V = r.L ** 3
+        assert a.attempts == b.attempts
+        # attempts count every launch: (iterations before stretching) + span x (the rest)
+        assert a.attempts % (r.n_walkers * V * cfg.sweeps) == 0
+        ja, jb = mix["jobs_kept"][r.id], alone["jobs_kept"][r.id]
+        sa, sta = ja.read_state()
+        sb, stb = jb.read_state()
+        assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+        assert ja.lnW.tobytes() == jb.lnW.tobytes()
+        jb.free()
+    for j in mix["jobs_kept"].values():
+        j.free()
+
+
 def test_wall_budget_censors_unfinished_jobs():
     reqs = poisson_requests(4, rate=100.0, seed=5, L_range=(12, 12), walker_choices=(64,))
     cfg = ServeConfig(sweeps=200, threshold=0.99, max_iterations=10_000, wall_budget=1.5)

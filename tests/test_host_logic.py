@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from paper_1502_07214_amd import analysis, campaign, workloads
+from paper_1502_07214_amd import analysis, campaign, serve, workloads
 from paper_1502_07214_amd.muca import muca_flatness
 from paper_1502_07214_amd.serve import TRANSITION, delta_mid, poisson_requests, tilted_weights
 
@@ -115,6 +115,23 @@ def test_host_flatness_is_min_over_mean(lo, hi):
     w = h[lo:hi + 1]
     assert muca_flatness(h, lo, hi) == pytest.approx(w.min() / w.mean(), rel=1e-15)
     assert muca_flatness(np.zeros(10, dtype=np.int64), lo, hi) == 0.0
+
+
+def test_iteration_span_waits_for_coverage_then_counts_entries():
+    """One launch per iteration until every bin of the window was visited;
+    then enough launches for entries_per_bin entries per window bin (rounded
+    up); entries_per_bin 0 keeps one launch."""
+    h = np.zeros(101, dtype=np.int64)
+    h[10:61] = 5
+    h[30] = 0
+    assert serve.iteration_span(h, 10, 60, 64, 500, 200) == 1      # a bin of the window unvisited
+    h[30] = 1
+    assert serve.iteration_span(h, 10, 60, 64, 500, 200) == 1      # 51 bins x 200 < 64 x 500
+    assert serve.iteration_span(h, 10, 60, 8, 100, 200) == 13      # ceil(51 x 200 / 800)
+    assert serve.iteration_span(h, 10, 60, 8, 100, 0) == 1
+    assert serve.iteration_span(h, 0, 100, 8, 100, 200) == 1       # bins outside the visited range
+    h[:] = 1
+    assert serve.iteration_span(h, 0, 100, 1, 1, 3) == 303
 
 
 def test_serve_summary_separates_censored_jobs():
