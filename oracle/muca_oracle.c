@@ -422,7 +422,12 @@ double orc_update_weights(int V, const int64_t *hist, double *lnW)
 /*   K restarts at 0 whenever an iteration reaches a bin no earlier one did: */
 /*   the estimates gathered before were sampled while part of the range was  */
 /*   out of reach, and averaging them in freezes their bias (measured: at    */
-/*   T < 1.1 it multiplied the iterations to flatness several times).        */
+/*   T < 1.1 it multiplied the iterations to flatness several times).  K     */
+/*   also restarts when an iteration leaves a bin unvisited between the      */
+/*   lowest and highest bins visited so far: the walkers stopped reaching    */
+/*   part of the range, the few entries near its edge barely move d against  */
+/*   the statistics gathered before, and the visited part would keep         */
+/*   shrinking (measured on windows spanning a first-order transition).      */
 /* flags & 2 (extrapolate): bins outside the range [lo, hi] of bins visited  */
 /*   in any iteration so far continue the slope of lnW over the last         */
 /*   k = min(8, hi - lo) bins inside the range, at each end.                  */
@@ -452,7 +457,21 @@ double orc_update_weights_window(int V, double beta, int lo, int hi, const int64
             seen[E] = 1;
         }
     }
-    if ((flags & 1u) && any_seen && reached_new)
+    /* a bin left unvisited inside the range visited so far */
+    int lost = 0;
+    {
+        int slo = -1, shi = -1;
+        for (int E = lo; E <= hi; E++)
+            if (seen[E]) {
+                if (slo < 0)
+                    slo = E;
+                shi = E;
+            }
+        for (int E = slo; slo >= 0 && E <= shi; E++)
+            if (hist[E] == 0)
+                lost = 1;
+    }
+    if ((flags & 1u) && any_seen && (reached_new || lost))
         for (int E = lo; E < hi; E++)
             kacc[E] = 0.0;
     if (flags & 1u) {

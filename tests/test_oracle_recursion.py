@@ -179,6 +179,34 @@ def test_accumulated_is_the_inverse_variance_mean_of_the_estimates():
         assert np.allclose(np.diff(job.lnW), num / den, rtol=0, atol=1e-10)
 
 
+def test_accumulated_statistics_restart_when_a_visited_bin_is_missed():
+    # after an iteration that leaves a bin unvisited between the lowest and
+    # highest bins visited so far, the step is the plain one again: with K
+    # restarted, each pair's weight k / K is 1 and the frontier pairs around
+    # the missed bin take the plain step anyway
+    h1 = np.array([0, 0, 30, 40, 50, 60, 0, 0, 0], dtype=np.int64)
+    h2 = np.array([0, 0, 60, 10, 0, 20, 0, 0, 0], dtype=np.int64)
+    a, p = fresh(2, flags=ACC), fresh(2, flags=0)
+    for h in (h1, h2):
+        a.update_weights(h)
+        p.update_weights(h)
+    assert np.allclose(np.diff(a.lnW)[1:7], np.diff(p.lnW)[1:7], rtol=0, atol=1e-12)
+    # with the bin visited, the second histogram is averaged with the first
+    h2c = np.array([0, 0, 60, 10, 5, 20, 0, 0, 0], dtype=np.int64)
+    b, q = fresh(2, flags=ACC), fresh(2, flags=0)
+    for h in (h1, h2c):
+        b.update_weights(h)
+        q.update_weights(h)
+    assert not np.allclose(np.diff(b.lnW)[2:5], np.diff(q.lnW)[2:5])
+    # a bin missed outside the visited range is no loss: 0 and 1 stay unseen
+    h3 = np.array([0, 0, 60, 10, 5, 20, 0, 0, 0], dtype=np.int64)
+    c = fresh(2, flags=ACC)
+    for h in (h1, h3):
+        c.update_weights(h)
+    assert np.allclose(c.kacc[2:5], [h1[E] * h1[E + 1] / (h1[E] + h1[E + 1]) + h3[E] * h3[E + 1] / (h3[E] + h3[E + 1])
+                                     for E in range(2, 5)], rtol=1e-15, atol=0)
+
+
 def test_accumulated_statistics_restart_when_the_range_grows():
     # after an iteration that reaches a new bin, the next step is the plain
     # one again (the earlier estimates carry the bias of the missing range)
