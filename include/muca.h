@@ -155,10 +155,11 @@ int muca_update_weights(muca_job *job, const int64_t *hist, double *lnW_out, dou
  *     weighted by its inverse Poisson variance H(E)H(E+1)/(H(E)+H(E+1)); a
  *     pair with one visited bin takes the plain step; lnW(0) is kept and the
  *     rest rebuilt from the differences.  The accumulated statistics restart
- *     whenever an iteration reaches a bin no earlier iteration did.  When the
- *     walkers stay trapped on either side of a strong first-order barrier, no
- *     new bin is reached and the steps keep shrinking; such jobs converge
- *     with MUCA_REC_EXTRAPOLATE alone or with the plain recursion.
+ *     whenever an iteration reaches a bin no earlier iteration did, or leaves
+ *     a bin unvisited between the lowest and highest bins visited so far
+ *     (walkers that stopped reaching part of the range, e.g. across a
+ *     first-order barrier, would otherwise leave it with steps too small to
+ *     bring them back).
  *   MUCA_REC_EXTRAPOLATE: bins outside the range visited in any iteration so
  *     far continue the mean slope of the last min(8, width) differences inside
  *     it, at each end.

@@ -562,7 +562,8 @@ namespace {
 // each iteration's estimate of the flat-histogram difference enters with its
 // inverse Poisson variance k = H(E) H(E+1) / (H(E) + H(E+1)); a pair with one
 // visited bin takes the plain step; the weights are rebuilt upwards from bin 0.
-// The caller restarts the sums when an iteration reaches a new bin.
+// The caller restarts the sums when an iteration reaches a new bin or misses
+// one inside the range visited so far.
 void accumulated_step(int lo, int hi, const int64_t *hist, double *lnW, double *kacc)
 {
     std::vector<double> d(std::max(hi, 1));
@@ -625,8 +626,21 @@ int muca_update_weights(muca_job *j, const int64_t *hist, double *lnW_out, doubl
         }
     }
     // estimates sampled before the range grew are biased by the part that was
-    // out of reach: the accumulated statistics restart
-    if ((j->rec_flags & MUCA_REC_ACCUMULATED) && any_seen && reached_new)
+    // out of reach: the accumulated statistics restart.  They restart too when
+    // the walkers stop reaching a bin inside the range visited so far: the few
+    // entries near that edge would barely move the weights against the
+    // statistics gathered before, and the visited part would keep shrinking.
+    bool missed = false;
+    {
+        int first = -1, last = -1;
+        for (int E = lo; E <= hi; ++E)
+            if (j->seen[E]) {
+                if (first < 0) first = E;
+                last = E;
+            }
+        for (int E = first; first >= 0 && E <= last && !missed; ++E) missed = hist[E] == 0;
+    }
+    if ((j->rec_flags & MUCA_REC_ACCUMULATED) && any_seen && (reached_new || missed))
         std::fill(j->kacc.begin() + lo, j->kacc.begin() + hi, 0.0);
     if (j->rec_flags & MUCA_REC_ACCUMULATED) {
         accumulated_step(lo, hi, hist, j->lnW.data(), j->kacc.data());

@@ -339,7 +339,12 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
     launch has finished merges each job's histogram, finishes the flat (or
     capped) ones and updates the others' weights, while the other lanes keep
     running.  Host resources of finished jobs are released at the end (their
-    release would wait for the whole device)."""
+    release would wait for the whole device).
+
+    Lanes only run independently if their streams do not share a hardware
+    queue: HIP maps a process's streams onto GPU_MAX_HW_QUEUES queues (4
+    unless set before HIP starts), so a process serving with n lanes wants at
+    least n + 1 of them (the lanes and the default stream)."""
     import torch
 
     t0 = time.perf_counter()
@@ -356,6 +361,7 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
     depth = []
     launches = 0
     attempts = 0
+    host = {"probes_s": 0.0, "launch_s": 0.0, "merge_s": 0.0}
     while pending or queue or any(l.active for l in lanes):
         now = time.perf_counter() - t0
         if cfg.wall_budget is not None and now >= cfg.wall_budget:
@@ -377,7 +383,9 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
             nbytes += fb
         if admit:
             # the admitted jobs' windows: their probes in one batched launch
+            th = time.perf_counter()
             windows = probe_windows(admit, cfg.probe, retired)
+            host["probes_s"] += time.perf_counter() - th
             for r in admit:
                 rec = JobRecord(r)
                 records[r.id] = rec
@@ -386,11 +394,13 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
                                          lane.stream if n_lanes > 1 else None))
                 lane.changed = True
         depth.append(len(queue))
+        th = time.perf_counter()
         for lane in lanes:
             if lane.active and not lane.in_flight:
                 lane.launch(cfg)
                 launches += 1
                 attempts += sum(a.rec.req.n_walkers * a.V for a in lane.members) * cfg.sweeps
+        host["launch_s"] += time.perf_counter() - th
         if not any(l.in_flight for l in lanes):
             if pending:
                 _wait_until(t0, pending[0].arrival if cfg.wall_budget is None
@@ -402,8 +412,10 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
                 continue
             lane.in_flight = False
             progressed = True
-            now = time.perf_counter() - t0
+            th = time.perf_counter()
+            now = th - t0
             done = [a for a in lane.members if a.step_done(cfg, now)]
+            host["merge_s"] += time.perf_counter() - th
             if not done:
                 continue
             if progress is not None:
@@ -437,6 +449,9 @@ def serve(requests: Sequence[Request], cfg: ServeConfig, keep_jobs: bool = False
     out = _summary(records, makespan, attempts, launches, depth, kept)
     out["not_arrived"] = len(pending)
     out["lanes"] = n_lanes
+    # host time of the loop: probes of admitted jobs, launches (including
+    # rebuilding a lane's batch), merges and weight updates
+    out["host_s"] = dict(host)
     return out
 
 

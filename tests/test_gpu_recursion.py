@@ -45,6 +45,44 @@ def test_recursion_variants_match_oracle(L, T, nw, flags):
     job.free()
 
 
+@pytest.mark.parametrize("L,T,nw,window", [(6, 1.0, 16, (30, 190)), (7, 0.95, 8, (60, 300))])
+def test_accumulated_restart_on_a_missed_bin_matches_oracle(L, T, nw, window):
+    """Windowed jobs below the tricritical temperature with few walkers and
+    short iterations, so that iterations leave bins of the visited range
+    unvisited and the accumulated statistics restart for that reason alone:
+    histograms and weights bit-identical to the oracle's after every
+    iteration, and such restarts did happen."""
+    say(f"[recursion] missed-bin restarts L={L} T={T} walkers={nw} window={window}")
+    lo, hi = window
+    flags = REC_ACCUMULATED | REC_EXTRAPOLATE
+    job = MucaJob(L, T, nw, seed=77, max_delta=1)
+    job.set_recursion(flags)
+    job.set_window(lo, hi)
+    o = oracle.OracleJob(L, T, nw, 77)
+    o.set_recursion(flags)
+    o.set_window(lo, hi)
+    missed_only = 0
+    for it in range(40):
+        job.sweep(60)
+        o.sweep(60)
+        h = job.reduce_hist()
+        ho = o.take_hist()
+        assert np.array_equal(h, ho), f"histogram differs at iteration {it}"
+        before = o.seen[lo:hi + 1].astype(bool)
+        now = h[lo:hi + 1] > 0
+        after = before | now
+        idx = np.nonzero(after)[0]
+        missed = len(idx) > 0 and bool((~now[idx[0]:idx[-1] + 1]).any())
+        if before.any() and missed and not (now & ~before).any():
+            missed_only += 1
+        assert job.update_weights(h) == o.update_weights(ho)
+        assert job.lnW.tobytes() == o.lnW.tobytes(), f"weights differ at iteration {it}"
+        kacc, seen = job.recursion_state()
+        assert kacc.tobytes() == o.kacc.tobytes() and np.array_equal(seen, o.seen)
+    assert missed_only > 0
+    job.free()
+
+
 def test_switching_recursion_restarts_its_statistics():
     L, T, nw = 4, 2.0, 16
     say("[recursion] switch")
