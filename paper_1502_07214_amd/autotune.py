@@ -20,8 +20,16 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache
 
 # (waves per walker, Philox blocks per lane, thresholds in LDS, packed lattices)
 PLAIN_SHAPES = [(w, b, t, p) for w in (4, 2, 1) for b in (1, 2) for t in (1, 0) for p in (0, 1) if b == 1 or p == 0]
-# (waves per walker, Philox blocks per lane, persistent blocks (0: fill), packed lattices)
+# (waves per walker, Philox blocks per lane, persistent blocks (0: as many as
+# fit on the device), packed lattices)
 BATCH_SHAPES = [(w, b, 0, p) for w in (0, 1, 2, 4) for b in (1, 2) for p in (0, 1) if b == 1 or p == 0]
+
+
+def batch_shapes(n_cu: int) -> list:
+    """BATCH_SHAPES, each also with two persistent blocks per compute unit:
+    fewer blocks than fit leave the long walkers of the largest lattices
+    fewer waves to share their SIMDs with."""
+    return [s for s in BATCH_SHAPES] + [(w, b, 2 * n_cu, p) for (w, b, _, p) in BATCH_SHAPES]
 
 
 def _device_name() -> str:
@@ -113,7 +121,7 @@ def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[
     as for tune_job: the batch is timed after that many iterations of every
     job.  ValueError if no candidate shape is valid."""
     sig = ",".join(f"{L}:{T!r}:{n}" for (L, T, n, _) in sorted(specs))
-    key = f"batch2|{_device_name()}|{sig}|warm{warm[0]}x{warm[1]}"
+    key = f"batch4|{_device_name()}|{sig}|warm{warm[0]}x{warm[1]}"
     data = _load(cache)
     if key in data:
         return tuple(data[key]["shape"])
@@ -123,12 +131,19 @@ def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[
         batch.sweep(warm[1])
         for c in clones:
             c.update_weights(c.reduce_hist())
+    # every candidate starts from the same walkers (the timed sweeps move them)
+    states = [c.read_state() for c in clones]
     best, best_ms, timings = None, float("inf"), {}
-    for shape in (BATCH_SHAPES if shapes is None else shapes):
+    if shapes is None:
+        import torch
+        shapes = batch_shapes(torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count)
+    for shape in shapes:
         try:
             batch.set_launch(*shape)
         except MucaError:
             continue
+        for c, (spins, state) in zip(clones, states):
+            c.write_state(spins, state)
         ms = _time(batch.sweep, probe_sweeps)
         timings[str(shape)] = ms
         if ms < best_ms:
@@ -144,9 +159,13 @@ def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[
     return best
 
 
-# warm-up of the benchmark tunings: (iterations, sweeps per iteration)
+# warm-up of the benchmark tunings: (iterations, sweeps per iteration).  The
+# batched workload is timed on weights past the first iterations: its later,
+# steeper iterations take most of its time, and the shape fastest on the
+# first ones (8 sites per lane, half the persistent blocks) is 15 % slower
+# over the whole workload.
 BENCH_WARM_PLAIN = (3, 2000)
-BENCH_WARM_BATCH = (3, 500)
+BENCH_WARM_BATCH = (6, 1000)
 
 
 def tune_benchmark_workloads(cache: str = CACHE) -> dict:
