@@ -27,8 +27,9 @@ import time
 # then waits for another lane's kernel (measured: the loop spent 27 of 40 s
 # blocked in such reads, with 40 % fewer launches).  Eight queues give each
 # lane and the default stream one of their own.  HIP reads the variable when
-# it starts, so it is set before torch is imported; a caller's value is kept.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# it starts, so it is set before torch is imported; a larger value is kept.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
