@@ -4,6 +4,7 @@
     python -m paper_1502_07214_amd.profile_runs sweep   # the benchmark's sweep launches (L=12, 256 walkers)
     python -m paper_1502_07214_amd.profile_runs saturation  # L=8, 65 536 walkers, 10 + 100 sweeps
     python -m paper_1502_07214_amd.profile_runs satgrid     # L=8, 12, 16 x 65 536 .. 262 144 walkers, 10 + 100 sweeps
+    python -m paper_1502_07214_amd.profile_runs served      # the served stream in asynchronous lanes, 40 s
     python -m paper_1502_07214_amd.profile_runs batched     # 19 mixed jobs: 10 batched launches of 1000 sweeps
     python -m paper_1502_07214_amd.profile_runs c3          # L=16, T=1, 1024 walkers: 3 iterations of 2*10^4 sweeps
     python -m paper_1502_07214_amd.profile_runs bigL L W P  # L^3, W walkers, packing P (0, 1, -1 auto): 3 x 200 sweeps
@@ -81,6 +82,23 @@ def saturation_grid():
         job.free()
 
 
+def served():
+    """The served stream as the benchmark serves it in asynchronous lanes
+    (200 jobs, L 8..24, 40 s wall budget), once."""
+    from . import REC_ACCUMULATED, REC_EXTRAPOLATE, workloads
+    from .serve import ServeConfig, poisson_requests, serve
+
+    sp = workloads.SERVED
+    reqs = poisson_requests(sp["n_jobs"], sp["rate"], sp["seed"], sp["L_range"], sp["T_range"], sp["walker_choices"],
+                            delta_halfwidth=sp["delta_halfwidth"])
+    cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"],
+                      wall_budget=sp["wall_budget"], recursion=REC_ACCUMULATED | REC_EXTRAPOLATE,
+                      lane_bounds=tuple(sp["lane_bounds"]), entries_per_bin=sp["entries_per_bin"])
+    r = serve(reqs, cfg)
+    print(f"served: {r['converged']} of {r['jobs']} flat, p50 {r['latency_p50_s']:.2f} s, "
+          f"{r['attempts_per_s']:.3e} attempts/s, {r['launches']} launches", flush=True)
+
+
 def batched():
     import torch
 
@@ -145,4 +163,4 @@ if __name__ == "__main__":
         bigL(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]))
     else:
         {"copy": copy, "sweep": sweep, "saturation": saturation, "satgrid": saturation_grid, "batched": batched,
-         "c3": c3}[sys.argv[1]]()
+         "c3": c3, "served": served}[sys.argv[1]]()
