@@ -181,7 +181,9 @@ class ServeConfig:
     max_iterations: int = 2000     # iteration cap (job censored)
     max_walkers: int = 32768       # resident walkers
     hbm_budget: int = 16 << 30     # resident device bytes
-    shape: Optional[Tuple[int, int]] = None  # batched launch shape (None: library default)
+    # batched launch shape (waves per walker, blocks per lane, persistent
+    # blocks, packing) of the lanes' batches; None: the library's default
+    shape: Optional[Tuple[int, int, int, int]] = None
     recursion: int = 0             # weight recursion flags (REC_ACCUMULATED | REC_EXTRAPOLATE; 0 plain)
     probe: ProbeConfig = field(default_factory=ProbeConfig)  # Delta range -> E_Delta window
     wall_budget: Optional[float] = None  # seconds; jobs unfinished by then are censored at it
