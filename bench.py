@@ -192,7 +192,8 @@ def served_leg():
     cfg = ServeConfig(sweeps=sp["sweeps"], threshold=sp["threshold"], max_iterations=sp["max_iterations"],
                       wall_budget=sp["wall_budget"], recursion=REC_ACC_EXT, lane_bounds=tuple(sp["lane_bounds"]),
                       entries_per_bin=sp["entries_per_bin"])
-    out = {"spec": {k: v for k, v in sp.items()}, "recursion": "accumulated+extrapolate"}
+    out = {"spec": {k: v for k, v in sp.items()}, "recursion": "accumulated+extrapolate",
+           "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))}
     modes = (("served_async", serve, cfg), ("served_lockstep", serve, dataclasses.replace(cfg, lane_bounds=())),
              ("one_at_a_time", serve_plain, cfg))
     for mode, fn, c in modes:
@@ -202,6 +203,8 @@ def served_leg():
                                        "attempts_per_s", "latency_p50_s", "latency_p99_s",
                                        "latency_converged_p50_s", "latency_converged_p99_s", "iterations_p50",
                                        "long_iteration_jobs", "queue_depth_max")}
+        if "host_s" in r:
+            out[mode]["host_s"] = {k: round(v, 3) for k, v in r["host_s"].items()}
     return out
 
 

@@ -117,6 +117,14 @@ def test_host_flatness_is_min_over_mean(lo, hi):
     assert muca_flatness(np.zeros(10, dtype=np.int64), lo, hi) == 0.0
 
 
+def test_lanes_split_jobs_by_lattice_size():
+    """Lane k holds L <= bounds[k] (and above the previous bound); the last
+    lane everything larger; no bounds: one lane."""
+    b = (12, 16, 20)
+    assert [serve.lane_of(L, b) for L in (8, 12, 13, 16, 17, 20, 21, 24)] == [0, 0, 1, 1, 2, 2, 3, 3]
+    assert serve.lane_of(24, ()) == 0
+
+
 def test_iteration_span_waits_for_coverage_then_counts_entries():
     """One launch per iteration until every bin of the window was visited;
     then enough launches for entries_per_bin entries per window bin (rounded
