@@ -3,9 +3,11 @@
 * Pseudo-critical point: Delta*_L maximises C(Delta) = d<E_J>/dDelta; it is
   located by bisection on the zero of dC/dDelta (the second field derivative of
   <E_J>), each evaluation a reweighting on the device.  C*_L = C(Delta*_L).
-* Jackknife: the production run is recorded in w consecutive time blocks; the
-  estimate is repeated on the w subsets that each leave one block out, and the
-  error is sqrt((w-1)/w sum (x_j - mean)^2).
+* Jackknife: the production run is recorded in w blocks, either consecutive
+  time blocks or groups of walkers (the paper's independent production runs:
+  each group's chains are independent of the others'); the estimate is
+  repeated on the w subsets that each leave one block out, and the error is
+  sqrt((w-1)/w sum (x_j - mean)^2).
 * Equal-height field: the Delta where the two peaks of the reweighted P(e_Delta)
   (maxima below and above a split bin) have equal height; the barrier
   ln(P_max / P_min) / (2 beta Delta_eqh) uses the minimum of P between them.
@@ -20,7 +22,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .muca import OBS_FIELDS, MucaJob
+from .muca import OBS_FIELDS, MucaBatch, MucaJob
 
 _DC = OBS_FIELDS.index("dC_dDelta")
 _C = OBS_FIELDS.index("C_field")
@@ -65,6 +67,46 @@ def production_blocks(job: MucaJob, n_blocks: int, sweeps: int) -> Tuple[List[di
         blocks.append(_minus(cur, prev))
         prev = cur
     return blocks, prev
+
+
+def walker_blocks(job: MucaJob, n_groups: int, sweeps: int) -> Tuple[List[dict], dict]:
+    """Record a production run of `sweeps` sweeps per group of walkers: the
+    job's walkers are split into n_groups contiguous ranges, each swept (in
+    one batched launch) as a sub-job holding that range (the same seed,
+    weights and window, so every walker runs its own chain of the job).
+    Afterwards the job holds the walkers' final states and the total sums,
+    as after reset_accum() and sweep(sweeps, record=True); its iteration
+    histogram is left as it was.  Returns the per-group sums and their total."""
+    if not 1 <= n_groups <= job.n_walkers:
+        raise ValueError("n_groups must lie in 1..n_walkers")
+    spins, state = job.read_state()
+    lo, hi = job.window
+    edges = [job.n_walkers * g // n_groups for g in range(n_groups + 1)]
+    weights = job.lnW
+    subs = []
+    try:
+        for g in range(n_groups):
+            a, b = edges[g], edges[g + 1]
+            sub = MucaJob(job.L, job.T, b - a, seed=job.seed, lnW=weights, max_delta=1, device=job.device,
+                          first_walker=job.first_walker + a)
+            subs.append(sub)
+            if (lo, hi) != (0, job.V):
+                sub.set_window(lo, hi)
+            sub.write_state(spins[a:b], state[a:b])
+        batch = MucaBatch(subs)
+        batch.sweep(sweeps, record=True)
+        batch.free()
+        blocks = [sub.read_accum() for sub in subs]
+        finals = [sub.read_state() for sub in subs]
+    finally:
+        for sub in subs:
+            sub.free()
+    total = _zero_sums(job.V)
+    for blk in blocks:
+        total = {k: ([x + y for x, y in zip(total[k], blk[k])] if k != "V" else total[k]) for k in total}
+    job.write_state(np.concatenate([f[0] for f in finals]), np.concatenate([f[1] for f in finals]))
+    job.write_accum(total)
+    return blocks, total
 
 
 def jackknife(values) -> Tuple[float, float]:

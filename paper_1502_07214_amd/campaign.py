@@ -10,6 +10,7 @@ through libmuca; this module sequences calls and picks brackets.
 
     python -m paper_1502_07214_amd.campaign            # the default points
     python -m paper_1502_07214_amd.campaign 8:1.0 12:2.0
+    python -m paper_1502_07214_amd.campaign --walker-groups 8:1.0   # jackknife over walker groups
 """
 from __future__ import annotations
 
@@ -69,7 +70,14 @@ def _bracket(grid: np.ndarray, values: np.ndarray):
 
 
 def run_point(L: int, T: float, walkers: int, sweeps: int, cap: int, n_blocks: int, block_sweeps: int,
-              recursion: int = REC_ACCUMULATED | REC_EXTRAPOLATE, seed: int = 0, grid=None, log=None) -> dict:
+              recursion: int = REC_ACCUMULATED | REC_EXTRAPOLATE, seed: int = 0, grid=None, log=None,
+              walker_groups: bool = False) -> dict:
+    """One point: weights to a flat histogram, production, the peak of C(Delta)
+    with jackknife errors and, below the tricritical temperature, the
+    equal-height field and barrier.  The production is n_blocks x block_sweeps
+    sweeps in consecutive time blocks, or (walker_groups) n_blocks x
+    block_sweeps sweeps of every walker with the walkers split into n_blocks
+    groups, the paper's independent runs."""
     t0 = time.perf_counter()
     dm = delta_mid(T)
     grid = np.linspace(dm - 1.0, dm + 0.5, 301) if grid is None else np.asarray(grid, dtype=np.float64)
@@ -77,8 +85,12 @@ def run_point(L: int, T: float, walkers: int, sweeps: int, cap: int, n_blocks: i
     job.set_recursion(recursion)
     out = {"L": L, "T": T, "walkers": walkers, "sweeps_per_iteration": sweeps, "recursion": recursion}
     out.update(converge(job, sweeps, cap, log=log))
-    blocks, total = analysis.production_blocks(job, n_blocks, block_sweeps)
+    if walker_groups:
+        blocks, total = analysis.walker_blocks(job, n_blocks, n_blocks * block_sweeps)
+    else:
+        blocks, total = analysis.production_blocks(job, n_blocks, block_sweeps)
     out["production_sweeps"] = n_blocks * block_sweeps
+    out["blocks"] = "walker groups" if walker_groups else "time blocks"
     cs = job.reweight_sums(total, grid)[:, _C]
     lo, hi, k = _bracket(grid, cs)
     out["scan_peak_at_edge"] = k in (0, len(grid) - 1)
@@ -111,13 +123,15 @@ def run_point(L: int, T: float, walkers: int, sweeps: int, cap: int, n_blocks: i
 
 def main(argv):
     pts = POINTS
+    walker_groups = "--walker-groups" in argv
+    argv = [a for a in argv if a != "--walker-groups"]
     if argv:
         want = [(int(a.split(":")[0]), float(a.split(":")[1])) for a in argv]
         pts = [p for p in POINTS if (p[0], p[1]) in want]
     for p in pts:
         print(f"[campaign] L={p[0]} T={p[1]}", file=sys.stderr, flush=True)
         log = lambda it, f: print(f"[campaign]   iteration {it}: flatness {f:.3f}", file=sys.stderr, flush=True)
-        print(json.dumps(run_point(*p, log=log)), flush=True)
+        print(json.dumps(run_point(*p, log=log, walker_groups=walker_groups)), flush=True)
 
 
 if __name__ == "__main__":

@@ -164,3 +164,49 @@ def test_jackknife_equal_height_matches_oracle():
     assert abs(jk["delta_eqh_err"] - de) < 1e-6 * max(de, 1e-6)
     assert abs(jk["barrier_err"] - be) < 1e-6 * max(be, 1e-6)
     job.free()
+
+
+@pytest.mark.parametrize("window", [None, (20, 50)])
+def test_walker_groups_replay_the_job_and_match_the_oracle(window):
+    """Production recorded per group of walkers (22 walkers in 5 ragged
+    groups): the job ends exactly as after its own recorded sweeps (sums and
+    every walker's state bit-identical to a twin job's), the groups' sums add
+    up to the total, and each group's sums equal the oracle's for that walker
+    range swept from the same state under the same weights."""
+    L, T, nw, seed, groups, sweeps = 4, 2.0, 22, 17, 5, 300
+    print(f"[analysis] walker groups window={window}", flush=True)
+    a = MucaJob(L, T, nw, seed=seed, max_delta=1)
+    b = MucaJob(L, T, nw, seed=seed, max_delta=1)
+    for j in (a, b):
+        if window is not None:
+            j.set_window(*window)
+        for _ in range(4):
+            j.sweep(200)
+            j.update_weights(j.reduce_hist())
+    spins0, state0 = a.read_state()
+    lnW = a.lnW
+    assert lnW.tobytes() == b.lnW.tobytes()
+    blocks, total = analysis.walker_blocks(a, groups, sweeps)
+    b.reset_accum()
+    b.sweep(sweeps, record=True)
+    assert a.read_accum() == b.read_accum() == total
+    sa, sta = a.read_state()
+    sb, stb = b.read_state()
+    assert np.array_equal(sa, sb) and np.array_equal(sta, stb)
+    for k in ("H", "SJ", "SJJ", "SA", "SM2", "SM4"):
+        assert [sum(col) for col in zip(*(blk[k] for blk in blocks))] == total[k]
+    edges = [nw * g // groups for g in range(groups + 1)]
+    for g in range(groups):
+        x, y = edges[g], edges[g + 1]
+        o = oracle.OracleJob(L, T, y - x, seed, lnW=lnW, first_walker=x)
+        if window is not None:
+            o.set_window(*window)
+        assert o.lnW.tobytes() == lnW.tobytes()
+        o.spins[:] = spins0[x:y]
+        o.state[:] = state0[x:y]
+        o.sweep(sweeps, record=True)
+        assert o.bin_sums() == blocks[g], f"group {g}"
+    with pytest.raises(ValueError):
+        analysis.walker_blocks(a, nw + 1, 1)
+    a.free()
+    b.free()
