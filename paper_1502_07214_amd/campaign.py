@@ -114,8 +114,14 @@ def run_point(L: int, T: float, walkers: int, sweeps: int, cap: int, n_blocks: i
         cross = [i for i in range(len(grid) - 1) if diffs[i] > 0 and diffs[i + 1] < 0]
         if cross:
             i = cross[0]
-            d_eqh, barrier = analysis.equal_height(job, float(grid[i]), float(grid[i + 1]), split)
-            out.update({"delta_eqh": d_eqh, "barrier": barrier, "split_bin": split})
+            out["split_bin"] = split
+            try:
+                eq = analysis.jackknife_equal_height(job, blocks, total, float(grid[i]), float(grid[i + 1]), split)
+                out.update({"delta_eqh": eq["delta_eqh"], "barrier": eq["barrier"],
+                            "delta_eqh_err": eq["delta_eqh_err"], "barrier_err": eq["barrier_err"]})
+            except ValueError as e:  # a block subset without a crossing on the bracket
+                d_eqh, barrier = analysis.equal_height(job, float(grid[i]), float(grid[i + 1]), split)
+                out.update({"delta_eqh": d_eqh, "barrier": barrier, "eqh_error": str(e)})
     out["seconds"] = time.perf_counter() - t0
     job.free()
     return out
