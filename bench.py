@@ -109,7 +109,8 @@ def batched_leg():
     one persistent launch per iteration over every job (lock-step), in the
     default and in the autotuned batch shape; asynchronous lanes (jobs grouped
     by L, each group a batch on its own stream iterating on its own); and one
-    plain launch per job."""
+    plain launch per job.  The three batched modes run twice, in turn, and
+    report the mean (one run varies by a few per cent)."""
     import torch
 
     from paper_1502_07214_amd import MucaBatch, MucaJob, autotune, workloads
@@ -117,10 +118,12 @@ def batched_leg():
     specs = workloads.batched_jobs()
     it, sw = workloads.BATCHED["iterations"], workloads.BATCHED["sweeps"]
     per_sweep = sum(n * L ** 3 for (L, T, n, s) in specs)
-    tuned = autotune.tune_batch(specs, probe_sweeps=500, cache=autotune.CACHE, warm=autotune.BENCH_WARM_BATCH)
+    tuned = autotune.tune_batch(specs, cache=autotune.CACHE, warm=autotune.BENCH_WARM_BATCH,
+                                **autotune.BENCH_BATCH_PROBE)
     out = {"jobs": len(specs), "walkers": sum(n for (_, _, n, _) in specs), "iterations": it, "sweeps": sw,
            "attempts": per_sweep * it * sw, "tuned_shape": list(tuned), "lanes": list(workloads.BATCHED_LANES)}
-    for mode in ("batched", "batched_tuned", "async_lanes", "plain"):
+    runs = {}
+    for mode in ("batched", "batched_tuned", "async_lanes") * 2 + ("plain",):
         jobs = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
         batches = []
         if mode in ("batched", "batched_tuned"):
@@ -165,9 +168,11 @@ def batched_leg():
                 for j in jobs:
                     j.update_weights(j.reduce_hist())
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        runs.setdefault(mode, []).append(time.perf_counter() - t0)
+        dt = sum(runs[mode]) / len(runs[mode])
         out[mode + "_attempts_per_s"] = out["attempts"] / dt
         out[mode + "_s"] = dt
+        out[mode + "_runs_s"] = list(runs[mode])
         for b in batches:
             b.free()
         for j in jobs:

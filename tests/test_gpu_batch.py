@@ -239,6 +239,13 @@ def test_tuned_shapes_keep_the_chain(tmp_path):
     assert np.array_equal(a.read_state()[0], b.read_state()[0])
     specs = [(8, 1.0, 16, 1), (12, 2.0, 8, 2), (6, 0.9, 12, 3)]
     bshape = autotune.tune_batch(specs, probe_sweeps=10, cache=cache)
+    # with finalists re-timed: a shape of the first pass, kept under its own key
+    fshape = autotune.tune_batch(specs, probe_sweeps=10, cache=cache, finalists=3, repeats=2)
+    entries = autotune._load(cache)
+    fkey = [k for k in entries if k.startswith("batch4|") and k.endswith("|final3x2")]
+    assert len(fkey) == 1 and list(fshape) == entries[fkey[0]]["shape"]
+    assert set(entries[fkey[0]]["finalists"]) <= set(entries[fkey[0]]["timings"])
+    assert str(tuple(fshape)) in entries[fkey[0]]["finalists"]
     ja = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
     jb = [MucaJob(L, T, n, seed=s, max_delta=1) for (L, T, n, s) in specs]
     ba, bb = MucaBatch(ja), MucaBatch(jb)
