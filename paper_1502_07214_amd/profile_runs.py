@@ -99,14 +99,22 @@ def served():
           f"{r['attempts_per_s']:.3e} attempts/s, {r['launches']} launches", flush=True)
 
 
-def batched():
+def batched(tuned: bool = False):
+    """The benchmark's batched workload, lock-step, in the default batch shape
+    or (tuned) in the one the benchmark tunes for it (from the committed
+    tuning cache)."""
     import torch
 
-    from . import MucaBatch, MucaJob, workloads
+    from . import MucaBatch, MucaJob, autotune, workloads
 
     specs = workloads.batched_jobs()
     jobs = [MucaJob(L, T, n, seed=sd, max_delta=1) for (L, T, n, sd) in specs]
     batch = MucaBatch(jobs)
+    if tuned:
+        shape = autotune.tune_batch(specs, cache=autotune.CACHE, warm=autotune.BENCH_WARM_BATCH,
+                                    **autotune.BENCH_BATCH_PROBE)
+        batch.set_launch(*shape)
+        print(f"batched launch {shape}", flush=True)
     for it in range(workloads.BATCHED["iterations"]):
         batch.sweep(workloads.BATCHED["sweeps"])
         for j in jobs:
@@ -163,4 +171,4 @@ if __name__ == "__main__":
         bigL(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]))
     else:
         {"copy": copy, "sweep": sweep, "saturation": saturation, "satgrid": saturation_grid, "batched": batched,
-         "c3": c3, "served": served}[sys.argv[1]]()
+         "batched_tuned": lambda: batched(tuned=True), "c3": c3, "served": served}[sys.argv[1]]()
