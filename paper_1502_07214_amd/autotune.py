@@ -188,8 +188,8 @@ def tune_batch(specs: Sequence[tuple], probe_sweeps: int = 100, cache: Optional[
 BENCH_WARM_PLAIN = (3, 2000)
 BENCH_WARM_BATCH = (6, 1000)
 # the batched workload's tuning: one iteration's sweeps per timing, and the
-# three fastest shapes timed three more times each
-BENCH_BATCH_PROBE = dict(probe_sweeps=1000, finalists=3, repeats=3)
+# six fastest shapes timed three more times each
+BENCH_BATCH_PROBE = dict(probe_sweeps=1000, finalists=6, repeats=3)
 
 
 def tune_benchmark_workloads(cache: str = CACHE) -> dict:
