@@ -83,7 +83,7 @@ def walker_blocks(job: MucaJob, n_groups: int, sweeps: int) -> Tuple[List[dict],
     lo, hi = job.window
     edges = [job.n_walkers * g // n_groups for g in range(n_groups + 1)]
     weights = job.lnW
-    subs = []
+    subs, batch = [], None
     try:
         for g in range(n_groups):
             a, b = edges[g], edges[g + 1]
@@ -95,10 +95,11 @@ def walker_blocks(job: MucaJob, n_groups: int, sweeps: int) -> Tuple[List[dict],
             sub.write_state(spins[a:b], state[a:b])
         batch = MucaBatch(subs)
         batch.sweep(sweeps, record=True)
-        batch.free()
         blocks = [sub.read_accum() for sub in subs]
         finals = [sub.read_state() for sub in subs]
     finally:
+        if batch is not None:
+            batch.free()
         for sub in subs:
             sub.free()
     total = _zero_sums(job.V)
