@@ -103,10 +103,12 @@ __device__ __forceinline__ uint4 unpack16(unsigned x)
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Proposal: the b-th (ascending) of the two spin values other than s.
+// Proposal: the b-th (ascending) of the two spin values other than s.  Over
+// the six cases that is b - 1, raised by one when s < b (s = -1: b; s = 0:
+// 2b - 1; s = +1: b - 1), one compare and an add with carry.
 __device__ __forceinline__ int propose(int s, int b)
 {
-    return b ? (s == 1 ? 0 : 1) : (s == -1 ? 0 : -1);
+    return b - 1 + (s < b ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -121,7 +123,7 @@ struct Walker {
     static_assert(!PACK || BPL == 1, "packed lattices are read one Philox block per lane");
     int8_t *lat;                         // this walker's lattice in LDS (PACK: 2-bit codes)
     const double *R;                     // [E][0] = R_-, [E][1] = R_+
-    const double *sBp;                   // B'[25] in LDS
+    const double *sBp;                   // B' in LDS, mirrored: sBp[12 + k] = B'(dE_J = -k)
     int *sX;                             // [2][4] per-wave exchange words
     int V, wave, lane, slot, wi, lg;
     uint32_t w32, k0, k1;
@@ -139,7 +141,7 @@ struct Walker {
         const int jb0 = jbase + lg * BPL;
         // ---- independent part: Philox words, neighbour sums, proposals ----
         double u[NS], bp[NS];
-        int dd[NS], dej[NS], dsg[NS], snew[NS], sold[NS];
+        int dd[NS], ndej[NS], dsg[NS], snew[NS], sold[NS];
         bool valid[NS];
         // spins first: their LDS latency overlaps the generator's rounds
         int words[BPL];
@@ -201,9 +203,9 @@ struct Walker {
                 sold[k] = s;
                 snew[k] = sn;
                 dsg[k] = sn - s;
-                dej[k] = -(sn - s) * h[t];
+                ndej[k] = (sn - s) * h[t];  // -dE_J
                 dd[k] = sn * sn - s * s;
-                bp[k] = sBp[dej[k] + 12];
+                bp[k] = sBp[ndej[k] + 12];
             }
         }
         // ---- sequential part: exact fixed point over E_Delta ----
@@ -380,7 +382,7 @@ struct Walker {
         unsigned nacc = 0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            myEJ += acc[k] ? (unsigned)dej[k] : 0u;
+            myEJ -= acc[k] ? (unsigned)ndej[k] : 0u;
             myM += acc[k] ? (unsigned)dsg[k] : 0u;
             nacc += acc[k] ? 1u : 0u;
         }
@@ -422,7 +424,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     const int lg = wk.lg, lane = wk.lane, wave = wk.wave, slot = wk.slot;
 
     // ---- stage tables and lattices in LDS ----
-    for (int k = tid; k < 32; k += kBlock) sBp[k] = (k < 25) ? a.bp[k] : 0.0;
+    // mirrored, so that a lane indexes it with -dE_J = (s' - s) h directly
+    for (int k = tid; k < 32; k += kBlock) sBp[k] = (k < 25) ? a.bp[24 - k] : 0.0;
     if (a.lds_hist)
         for (int e = tid; e <= V; e += kBlock) sHist[e] = 0u;
     const double *R = a.r + 2 * kRPad;  // R[2E + 1] = R_+(E), R[2E] = R_-(E), E in [-kRPad, V + kRPad]
