@@ -199,7 +199,15 @@ class ServeConfig:
     entries_per_bin: int = 0
 
 
-def iteration_span(hist: np.ndarray, lo: int, hi: int, n_walkers: int, sweeps: int, entries_per_bin: int) -> int:
+# entries per window bin, above ln B, below which one launch counts as too
+# short to cover a window of B bins (see iteration_span): with ln B + 3, B
+# independent Poisson counts are all nonzero with probability exp(-e^-3) =
+# 0.95, and the entries of a Markov chain are fewer independent ones than that
+SHORT_LAUNCH_MARGIN = 3.0
+
+
+def iteration_span(hist: np.ndarray, lo: int, hi: int, n_walkers: int, sweeps: int, entries_per_bin: int,
+                   seen: Optional[np.ndarray] = None) -> int:
     """Launches of `sweeps` sweeps per iteration after an iteration whose
     histogram is `hist`.
 
@@ -213,10 +221,21 @@ def iteration_span(hist: np.ndarray, lo: int, hi: int, n_walkers: int, sweeps: i
     has been visited the weights are close enough that longer iterations
     only sharpen the test, and the iteration is stretched to about
     entries_per_bin entries per bin; before that, short iterations let the
-    recursion move the weights quickly."""
-    if entries_per_bin <= 0 or not np.all(hist[lo:hi + 1] > 0):
+    recursion move the weights quickly.
+
+    A launch with fewer than ln B + SHORT_LAUNCH_MARGIN entries per bin on
+    average over the B window bins leaves some bin empty often even under
+    flat weights (all B Poisson counts are nonzero with probability
+    exp(-B e^-m) at m entries per bin), so its iterations rarely show a
+    covered window.  There the window counts as covered once the iterations
+    so far (`seen`, the bins any of them visited) have covered it."""
+    bins = hi - lo + 1
+    covered = bool(np.all(hist[lo:hi + 1] > 0))
+    if not covered and seen is not None and n_walkers * sweeps < bins * (math.log(bins) + SHORT_LAUNCH_MARGIN):
+        covered = bool(np.all(seen[lo:hi + 1]))
+    if entries_per_bin <= 0 or not covered:
         return 1
-    return max(1, math.ceil(entries_per_bin * (hi - lo + 1) / (n_walkers * sweeps)))
+    return max(1, math.ceil(entries_per_bin * bins / (n_walkers * sweeps)))
 
 
 class _Live:
@@ -237,6 +256,7 @@ class _Live:
         rec.admitted = now
         self.span = 1      # launches per iteration
         self.launches = 0  # launches of the iteration in progress
+        self.seen = np.zeros(self.V + 1, dtype=bool)  # bins visited by any iteration so far
 
     def step_done(self, cfg: ServeConfig, now: float) -> bool:
         """After a launch: at the end of an iteration, merge its histogram
@@ -258,8 +278,9 @@ class _Live:
             return True
         self.job.update_weights(h)
         if self.span == 1:
+            self.seen |= h > 0
             self.span = rec.span = iteration_span(h, self.lo, self.hi, rec.req.n_walkers, cfg.sweeps,
-                                                  cfg.entries_per_bin)
+                                                  cfg.entries_per_bin, seen=self.seen)
         return False
 
 

@@ -142,6 +142,27 @@ def test_iteration_span_waits_for_coverage_then_counts_entries():
     assert serve.iteration_span(h, 0, 100, 1, 1, 3) == 303
 
 
+def test_iteration_span_counts_earlier_coverage_for_short_launches():
+    """A launch with fewer than ln B + 3 entries per window bin (B bins) often
+    leaves bins empty even under flat weights; there the bins that earlier
+    iterations visited count towards coverage.  Longer launches still need
+    one iteration that covers the window."""
+    B = 5000
+    h = np.ones(B + 1, dtype=np.int64)
+    h[100] = 0                                   # this iteration missed a bin
+    seen = np.ones(B + 1, dtype=bool)            # an earlier one visited it
+    # 64 x 500 = 32 000 entries < 5001 x (ln 5001 + 3) = 57 600: counts seen
+    assert serve.iteration_span(h, 0, B, 64, 500, 200) == 1
+    assert serve.iteration_span(h, 0, B, 64, 500, 200, seen=seen) == 32   # ceil(5001 x 200 / 32 000)
+    seen[200] = False
+    assert serve.iteration_span(h, 0, B, 64, 500, 200, seen=seen) == 1
+    seen[200] = True
+    # 128 x 500 = 64 000 entries > 57 600: one iteration must cover the window
+    assert serve.iteration_span(h, 0, B, 128, 500, 200, seen=seen) == 1
+    h[100] = 1
+    assert serve.iteration_span(h, 0, B, 128, 500, 200, seen=seen) == 16  # ceil(5001 x 200 / 64 000)
+
+
 def test_serve_summary_separates_censored_jobs():
     from paper_1502_07214_amd.serve import JobRecord, Request, _summary
     recs = {}
