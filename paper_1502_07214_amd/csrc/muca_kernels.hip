@@ -127,6 +127,7 @@ struct Walker {
     int *sX;                             // [2][4] per-wave exchange words
     int V, wave, lane, slot, wi, lg;
     uint32_t w32, k0, k1;
+    uint32_t rk[WPW == 4 ? 20 : 1];      // round keys in vector registers (four waves per walker)
     int ED;                              // E_Delta of the walker (uniform)
     int parity;                          // exchange buffer in use (alternates)
     unsigned myEJ, myM;                  // this lane's accepted E_J and M changes (mod 2^32)
@@ -176,15 +177,25 @@ struct Walker {
         __builtin_amdgcn_sched_barrier(0);
         // the round keys are cheap to rebuild; keeping them live across
         // passes would only spill them
-        uint32_t kk0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k0);
-        uint32_t kk1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k1);
-        asm volatile("" : "+s"(kk0), "+s"(kk1));
+        // Walkers of four waves (latency-bound: one wave per SIMD) take the
+        // round keys from vector registers; the others rebuild them here, as
+        // keeping them live across passes would only spill them.
+        uint32_t kk0 = 0u, kk1 = 0u;
+        if constexpr (WPW != 4) {
+            kk0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k0);
+            kk1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k1);
+            asm volatile("" : "+s"(kk0), "+s"(kk1));
+        }
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
             const int jb = jb0 + q;
             const bool blk = jb < j1;
             const int jbc = blk ? jb : j0;
-            const Ctr4 x = philox10((uint32_t)jbc, w32, sweep, 0u, kk0, kk1);
+            Ctr4 x;
+            if constexpr (WPW == 4)
+                x = philox10_rk((uint32_t)jbc, w32, sweep, 0u, rk);
+            else
+                x = philox10((uint32_t)jbc, w32, sweep, 0u, kk0, kk1);
             const int word = words[q];
             int h[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -475,6 +486,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int walker_base, 
     wk.w32 = (uint32_t)(a.w0 + walker);  // the global walker index keys the chain
     wk.k0 = a.k0;
     wk.k1 = a.k1;
+    if constexpr (WPW == 4) philox_round_keys(a.k0, a.k1, wk.rk);
     wk.myEJ = 0u;
     wk.myM = 0u;
 
