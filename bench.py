@@ -58,7 +58,7 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # FETCH_SIZE + WRITE_SIZE from rocprofv3, each scaled by the same counter's
 # reading on a plain 1 GiB copy (profiles/sweep_kernel_l12_t2_w256_pmc.txt).
 TRAFFIC_KERNEL = "muca_sweep_kernel<4, 1, false, true, 2, false>"
-TRAFFIC_BYTES_PER_LAUNCH = 2321010
+TRAFFIC_BYTES_PER_LAUNCH = 2316231
 # weight recursions of the convergence legs (flags of muca_set_recursion)
 REC_EXTRAPOLATE, REC_ACC_EXT = 2, 3
 
