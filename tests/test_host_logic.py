@@ -3,6 +3,7 @@ tilted starts, the jackknife, the campaign's convergence loop and brackets, the
 batched job table, the serving summary, and the library's host-only flatness
 measure."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -174,3 +175,17 @@ def test_serve_summary_separates_censored_jobs():
     assert out["latency_p99_s"] == pytest.approx(np.percentile([1, 2, 3, 50], 99))
     assert out["latency_converged_p99_s"] == pytest.approx(np.percentile([1, 2, 3], 99))
     assert out["latency_converged_p50_s"] == 2.0 and out["queue_depth_max"] == 2
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: asked for more it prints one JSON line
+    saying so and exits with status 2, before touching the device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
